@@ -1,0 +1,107 @@
+/*
+ * Oracle for the batched trust-region Newton (TRON) solve and the component ADMM step.
+ *
+ * TEST INFRASTRUCTURE ONLY. A plain, slow, FP64 CPU implementation of what the GPU
+ * library computes. It exists to check the GPU library and to time a CPU baseline.
+ * The GPU library includes nothing from here and this code includes nothing from the
+ * GPU library; only the test suite, the smoke check and the benchmark's CPU-baseline
+ * leg load it.
+ *
+ * Paper: Y. Kim, F. Pacaud, K. Kim, M. Anitescu, "Leveraging GPU batching for scalable
+ * nonlinear programming through massive Lagrangian decomposition", arXiv 2106.14995.
+ * Citations below name the paper's sections, equations, algorithm and figures.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC (no contraction, so every
+ * product and sum rounds on its own, in the order written).
+ */
+#ifndef TRON_ORACLE_H
+#define TRON_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Problem families (same numbering as the GPU library's public enum; an interface). */
+enum { OR_QP4 = 0, OR_BR6 = 1, OR_HS45M = 2 };
+/* Per-instance outcomes. */
+enum { OR_CONVERGED = 0, OR_MAX_ITER = 1, OR_STALLED = 2, OR_NONFINITE = 3, OR_BAD_BOUNDS = 4 };
+
+typedef struct {
+    double gtol;     /* absolute bound on the infinity norm of the projected gradient      */
+    int32_t max_iter;
+    int32_t use_warm;/* 1: take delta / alpha_c from the in/out arrays where they are > 0 */
+    double cg_rtol;  /* relative residual tolerance of the conjugate-gradient solve        */
+    double delta0;   /* > 0: initial trust radius for all instances; <= 0: cold rule      */
+} or_opts;
+
+/* Number of doubles in one instance's parameter block. */
+int64_t or_param_size(int32_t family, int32_t n);
+
+/* Per-instance statistics written by or_tron_batch when stats != NULL, OR_NSTAT doubles each:
+ * [0] algorithmic flops, [1] outer iterations, [2] CG iterations, [3] Cholesky attempts,
+ * [4] Cauchy trials, [5] projected-search trials, [6] subspace passes, [7] accepted steps. */
+#define OR_NSTAT 8
+
+/* Solve `batch` independent problems min f(x) s.t. lo <= x <= hi (eq. prob, Algorithm 1).
+ * n_per (length batch) gives each instance's size, or is NULL and n_uniform is used.
+ * Parameter blocks and vectors are packed back to back in instance order.
+ * delta / alphac (length batch, may be NULL) are read when opt->use_warm and written on exit.
+ * nthreads <= 0 uses every online host core. Returns the number of threads used. */
+int32_t or_tron_batch(int32_t family, int64_t batch, const int32_t *n_per, int32_t n_uniform,
+                      const double *params, const double *lo, const double *hi, const double *x0,
+                      double *x, double *f, int32_t *status, int32_t *iters,
+                      double *delta, double *alphac, double *stats,
+                      const or_opts *opt, int32_t nthreads);
+
+/* Family evaluations (for the tests): f, gradient, dense row-major Hessian. */
+double or_eval_f(int32_t family, int32_t n, const double *params, const double *x);
+void or_eval_g(int32_t family, int32_t n, const double *params, const double *x, double *g);
+void or_eval_h(int32_t family, int32_t n, const double *params, const double *x, double *h);
+/* Branch flows (p_ij, q_ij, p_ji, q_ji) at x for a BR6 parameter block. */
+void or_br6_flows(const double *params, const double *x, double *pq4);
+
+/* Core operations (Fig. "Core operations"), exposed for the tests. */
+int32_t or_ccf(int32_t m, const double *a, double alpha, double *l);      /* 0 on success   */
+void or_trsv_lower(int32_t m, const double *l, double *b);               /* L y = b, in place   */
+void or_trsv_lower_t(int32_t m, const double *l, double *b);             /* L^T y = b, in place */
+double or_trqsol(int32_t m, const double *x, const double *p, double delta);
+void or_breakpt(int32_t n, const double *x, const double *lo, const double *hi, const double *w,
+                int32_t *nbrpt, double *brptmin, double *brptmax);
+void or_gpstep(int32_t n, const double *x, const double *lo, const double *hi, double alpha,
+               const double *w, double *s);
+double or_projgrad_inf(int32_t n, const double *x, const double *lo, const double *hi,
+                       const double *g);
+/* Preconditioned CG of the subspace step on a dense m x m block (for the tests).
+ * r: model gradient on the block; returns the exit code (0 converged, 1 max iterations,
+ * 2 negative curvature, 3 trust boundary); w receives L^{-T} s_hat, *iters the count. */
+int32_t or_subspace_cg(int32_t m, const double *a, const double *r, double delta, double cg_rtol,
+                       double *w, double *shat, int32_t *iters, double *shift_out);
+
+/* ---------------- component ADMM (section "Distributed control of ACOPF") ---------------- */
+typedef struct {
+    int32_t nbus, nbranch, ngen, ref_bus;
+    double rho, base_mva;
+    const int32_t *br_from, *br_to;   /* nbranch each                                      */
+    const double *br_adm;             /* nbranch x 8: g_ij b_ij gc_ij bc_ij g_ji b_ji gc_ji bc_ji */
+    const double *br_lo, *br_hi;      /* nbranch x 6 bounds on (v_i v_j th_i th_j z_ij z_ji) */
+    const int32_t *gen_bus;           /* ngen                                              */
+    const double *gen_cost;           /* ngen x 2: c2 c1 (per MW^2, per MW)                 */
+    const double *gen_lim;            /* ngen x 4: pmin pmax qmin qmax (per unit)           */
+    const double *bus_load;           /* nbus x 4: pd qd gsh bsh (per unit)                 */
+} or_network;
+
+/* Flat state layout (doubles): 6*ngen + 30*nbranch + 2*nbus, see or_admm_state_size. */
+int64_t or_admm_state_size(const or_network *net);
+void or_admm_init(const or_network *net, double *state);
+/* Run `iters` iterations in place; resid receives (primal, dual) per iteration (2*iters). */
+int32_t or_admm_run(const or_network *net, double *state, int32_t iters, double *resid,
+                    const or_opts *opt, int32_t nthreads);
+/* One phase (0 generators, 1 branches, 2 buses, 3 multipliers) in place, for the tests. */
+int32_t or_admm_phase(const or_network *net, double *state, int32_t phase, double *out,
+                      const or_opts *opt, int32_t nthreads);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,234 @@
+"""Pins of the oracle's whole TRON solve (Algorithm 1) against things the mathematics fixes:
+brute-force active-set solutions of strictly convex box QPs, the closed form of separable
+quartics, the paper's hs45 variant, zero-residual branch problems, SciPy's L-BFGS-B, and the
+first- and second-order optimality conditions."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.optimize as so
+
+from paper_2106_14995_amd import workloads as W
+
+
+class Arr:
+    """A minimal batch made from explicit arrays."""
+
+    def __init__(self, family, ns, params, lo, hi, x0):
+        self.family = family
+        self.n = np.asarray(ns, dtype=np.int32)
+        self.params = np.concatenate(params) if params else np.zeros(0)
+        self.lo, self.hi, self.x0 = (np.concatenate(v) for v in (lo, hi, x0))
+
+
+def qp4_params(Q, c, kap):
+    n = Q.shape[0]
+    return np.concatenate([Q[np.tril_indices(n)], c, [kap]])
+
+
+def brute_force_box_qp(Q, c, lo, hi):
+    """The unique KKT point of min x'Qx/2 + c'x on [lo, hi] (Q positive definite), by trying
+    all 3^n patterns of (at lower, free, at upper)."""
+    n = len(c)
+    found = []
+    for pat in itertools.product((0, 1, 2), repeat=n):
+        pat = np.array(pat)
+        x = np.where(pat == 0, lo, np.where(pat == 2, hi, 0.0))
+        F = pat == 1
+        if F.any():
+            rhs = -c[F] - Q[np.ix_(F, ~F)] @ x[~F]
+            x[F] = np.linalg.solve(Q[np.ix_(F, F)], rhs)
+            if np.any(x[F] < lo[F] - 1e-12) or np.any(x[F] > hi[F] + 1e-12):
+                continue
+        g = Q @ x + c
+        if np.any(g[pat == 0] < -1e-10) or np.any(g[pat == 2] > 1e-10):
+            continue
+        found.append(x)
+    assert len(found) >= 1
+    return found[0]
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_box_qp_brute_force(orc, n):
+    rng = np.random.default_rng(1000 + n)
+    insts = []
+    for _ in range(12):
+        a = rng.standard_normal((n, n))
+        Q = a.T @ a + 0.1 * np.eye(n)
+        c = 4.0 * rng.standard_normal(n)  # large enough that many bounds are active
+        lo = rng.uniform(-2, -0.5, n)
+        hi = rng.uniform(0.5, 2, n)
+        insts.append((Q, c, lo, hi))
+    bt = Arr(0, [n] * len(insts), [qp4_params(Q, c, 0.0) for Q, c, _, _ in insts],
+             [i[2] for i in insts], [i[3] for i in insts], [np.zeros(n)] * len(insts))
+    r = orc.solve(bt, gtol=1e-11, nthreads=1)
+    assert np.all(r["status"] == 0)
+    nact = 0
+    for k, (Q, c, lo, hi) in enumerate(insts):
+        xs = brute_force_box_qp(Q, c, lo, hi)
+        x = r["x"][k * n:(k + 1) * n]
+        assert np.abs(x - xs).max() <= 1e-9
+        nact += int(np.sum((xs == lo) | (xs == hi)))
+    assert nact > 0  # the cases exercise active bounds
+
+
+def cardano_root(q, c, kap):
+    """Unique real root of 4 kap x^3 + q x + c = 0 (q, kap > 0)."""
+    p = q / (4 * kap)
+    r = c / (4 * kap)
+    s = math.sqrt(r * r / 4 + p ** 3 / 27)
+    cbrt = lambda v: math.copysign(abs(v) ** (1 / 3), v)
+    return cbrt(-r / 2 + s) + cbrt(-r / 2 - s)
+
+
+def test_separable_quartic_closed_form(orc):
+    rng = np.random.default_rng(77)
+    n = 7
+    insts = []
+    for _ in range(10):
+        q = rng.uniform(0.1, 3.0, n)
+        c = 3.0 * rng.standard_normal(n)
+        kap = 0.1
+        lo = rng.uniform(-2, -0.5, n)
+        hi = rng.uniform(0.5, 2, n)
+        insts.append((q, c, kap, lo, hi))
+    bt = Arr(0, [n] * 10, [qp4_params(np.diag(q), c, kap) for q, c, kap, _, _ in insts],
+             [i[3] for i in insts], [i[4] for i in insts], [np.zeros(n)] * 10)
+    r = orc.solve(bt, gtol=1e-11, nthreads=1)
+    assert np.all(r["status"] == 0)
+    for k, (q, c, kap, lo, hi) in enumerate(insts):
+        xs = np.array([min(max(cardano_root(q[i], c[i], kap), lo[i]), hi[i]) for i in range(n)])
+        assert np.abs(r["x"][k * n:(k + 1) * n] - xs).max() <= 1e-9
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+def test_hs45m_known_optimum(orc, n):
+    """The paper's modified hs45: f = 120 - prod x_i with x_i <= i has x*_i = i (section 4.2
+    footnote), so f* = 120 - n!."""
+    bt = W.hs45m_batch(4, n)
+    r = orc.solve(bt, gtol=1e-9, nthreads=1)
+    assert np.all(r["status"] == 0)
+    assert np.allclose(r["x"].reshape(4, n), np.arange(1, n + 1), atol=1e-12)
+    assert np.allclose(r["f"], 120.0 - math.factorial(n), rtol=1e-14)
+
+
+def test_br6_zero_residual(orc):
+    """Targets equal to the couplings of a feasible point and no multipliers: f >= 0 with
+    f = 0 only at that point (the theta terms pin both angles)."""
+    bt = W.br6_zero_residual(64)
+    r = orc.solve(bt, gtol=1e-9, nthreads=1)
+    assert np.all(r["status"] == 0)
+    assert np.abs(r["x"] - bt.xstar).max() <= 1e-7
+    assert np.abs(r["f"]).max() <= 1e-12
+
+
+def test_qp4_config0_against_lbfgsb(orc):
+    bt = W.qp4_batch(32, 8, config_id=0)
+    r = orc.solve(bt, gtol=1e-10, nthreads=1)
+    assert np.all(r["status"] == 0)
+    for k in range(32):
+        n, p, lo, hi, x0 = bt.instance(k)
+        f = lambda z: orc.eval_f(0, n, p, z)
+        g = lambda z: orc.eval_g(0, n, p, z)
+        res = so.minimize(f, x0, jac=g, method="L-BFGS-B", bounds=list(zip(lo, hi)),
+                          options=dict(ftol=1e-16, gtol=1e-12, maxiter=10000))
+        xo = r["x"][k * n:(k + 1) * n]
+        assert r["f"][k] <= res.fun + 1e-12
+        assert abs(r["f"][k] - res.fun) <= 1e-8 * max(1, abs(res.fun))
+        assert np.abs(xo - res.x).max() <= 1e-5
+        # a posteriori: strong convexity mu >= 0.1 bounds the distance to x* by the
+        # projected-gradient residual ||x - P(x - grad)|| times (1 + Lip)/mu
+        Q = np.zeros((n, n)); Q[np.tril_indices(n)] = p[:n * (n + 1) // 2]
+        Q = Q + Q.T - np.diag(np.diag(Q))
+        lip = np.linalg.eigvalsh(Q).max() + 12 * 0.1 * 4.0
+        resid = np.linalg.norm(xo - np.clip(xo - g(xo), lo, hi))
+        assert resid * (1 + lip) / 0.1 <= 1e-7
+
+
+def kkt_check(orc, family, n, p, lo, hi, x, gtol):
+    g = orc.eval_g(family, n, p, x)
+    assert np.all(x >= lo) and np.all(x <= hi)
+    assert orc.projgrad_inf(x, lo, hi, g) <= gtol
+    # second-order necessary condition on the free variables
+    F = (x > lo) & (x < hi)
+    if F.any():
+        H = orc.eval_h(family, n, p, x)
+        ev = np.linalg.eigvalsh(H[np.ix_(F, F)])
+        assert ev.min() >= -1e-8 * max(1.0, np.abs(ev).max())
+
+
+def test_br6_config1_optimality(orc):
+    bt = W.br6_batch(512)
+    r = orc.solve(bt, nthreads=1)
+    assert np.all(r["status"] == 0)
+    for k in range(0, 512, 7):
+        n, p, lo, hi, _ = bt.instance(k)
+        kkt_check(orc, 1, n, p, lo, hi, r["x"][6 * k:6 * k + 6], 1e-6)
+
+
+def test_status_codes(orc):
+    n = 3
+    Q = np.eye(n); c = np.ones(n)
+    p = qp4_params(Q, c, 0.1)
+    lo = -np.ones(n); hi = np.ones(n)
+    bad_lo = lo.copy(); bad_lo[1] = 2.0
+    nan_x = np.array([0.0, np.nan, 0.0])
+    bt = Arr(0, [n] * 3, [p, p, p], [lo, bad_lo, lo], [hi, hi, hi], [np.zeros(n), np.zeros(n), nan_x])
+    r = orc.solve(bt, nthreads=1)
+    assert list(r["status"]) == [0, 4, 3]
+    # max_iter = 1 on an instance that needs more
+    bt1 = W.qp4_batch(4, 8, config_id=0)
+    r1 = orc.solve(bt1, max_iter=1, nthreads=1)
+    assert np.all(r1["status"] == 1) and np.all(r1["iters"] == 1)
+    # gtol = 0 cannot be met: the run ends without claiming convergence
+    r0 = orc.solve(bt1, gtol=0.0, max_iter=60, nthreads=1)
+    assert np.all(r0["status"] != 0)
+
+
+def test_fixed_variables_and_start_at_solution(orc):
+    n = 4
+    rng = np.random.default_rng(4)
+    a = rng.standard_normal((n, n)); Q = a.T @ a + np.eye(n)
+    c = rng.standard_normal(n)
+    lo = np.array([-1.0, 0.3, -1.0, -1.0]); hi = np.array([1.0, 0.3, 1.0, 1.0])  # x1 fixed
+    bt = Arr(0, [n], [qp4_params(Q, c, 0.1)], [lo], [hi], [np.zeros(n)])
+    r = orc.solve(bt, gtol=1e-10, nthreads=1)
+    assert r["status"][0] == 0 and r["x"][1] == 0.3
+    bt2 = Arr(0, [n], [qp4_params(Q, c, 0.1)], [lo], [hi], [r["x"]])
+    r2 = orc.solve(bt2, gtol=1e-10, nthreads=1)
+    assert r2["status"][0] == 0 and r2["iters"][0] == 0
+    assert np.array_equal(r2["x"], r["x"])
+
+
+def test_iterates_feasible_and_packing_invariant(orc):
+    """Every instance is solved on its own: a subset, reordered, gives identical bits."""
+    bt = W.qp4_uneven_batch(40, 4, 16, config_id=3)
+    r = orc.solve(bt, nthreads=3)
+    vo = bt.voff()
+    assert np.all(r["x"] >= bt.lo) and np.all(r["x"] <= bt.hi)
+    idx = [17, 3, 39, 0, 22]
+    sub = bt.subset(idx)
+    rs = orc.solve(sub, nthreads=1)
+    svo = sub.voff()
+    for j, b in enumerate(idx):
+        assert np.array_equal(rs["x"][svo[j]:svo[j + 1]], r["x"][vo[b]:vo[b + 1]])
+        assert rs["f"][j] == r["f"][b] and rs["iters"][j] == r["iters"][b]
+
+
+def test_flop_counter_is_algorithmic(orc):
+    """The counter grows with the work done: more iterations, more flops; a converged start
+    counts only the first evaluation."""
+    bt = W.qp4_batch(16, 8, config_id=0)
+    r = orc.solve(bt, nthreads=1)
+    fl = r["stats"][:, 0]
+    assert np.all(fl > 0)
+    it = r["iters"]
+    assert np.corrcoef(fl, it)[0, 1] > 0.5
+    bt2 = Arr(0, [8] * 16, [bt.instance(k)[1] for k in range(16)],
+              [bt.instance(k)[2] for k in range(16)], [bt.instance(k)[3] for k in range(16)],
+              [r["x"][8 * k:8 * k + 8] for k in range(16)])
+    r2 = orc.solve(bt2, nthreads=1)
+    n = 8
+    first_eval = (2 * n * n + 7 * n + 4) + (2 * n * n + 5 * n + 1)
+    assert np.all(r2["stats"][:, 0] == first_eval)
