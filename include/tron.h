@@ -1,0 +1,170 @@
+/*
+ * tron.h -- C ABI of the MI355X batched trust-region Newton library.
+ *
+ * The library solves many small bound-constrained nonlinear programs at once,
+ *     minimize f(x)  subject to  l <= x <= u,   x in R^n            (eq. prob, section 1)
+ * with the trust-region Newton method of Algorithm 1 ("ExaTron's algorithm", section 3):
+ * Cauchy point, free-subspace identification, complete Cholesky preconditioner of the
+ * shifted reduced Hessian (section 4.3), trust-region preconditioned CG, back-transform,
+ * projected line search, convergence on the infinity norm of the projected gradient
+ * (section 5.1), with the ratio test and radius update of the TRON method the paper cites.
+ * It also runs the component ADMM of the paper's power-flow application (section 6.1:
+ * generator and branch subproblems, then buses, then multipliers), whose branch
+ * subproblems (eq. exp-branch) are the batched solves.
+ *
+ * Conventions shared by every call:
+ *  - All d_* pointers are device memory owned by the caller (any HIP allocation on the
+ *    current device). Host pointers are named without the prefix and are copied before the
+ *    call returns.
+ *  - Every call is stream-ordered and asynchronous on `stream` (a hipStream_t, NULL = the
+ *    null stream); results are valid once the stream has been synchronised.
+ *  - Calls never throw and never abort; they return a tron_err. tron_last_error() returns a
+ *    message for the calling thread's last failure.
+ *  - A handle is not thread-safe; different handles may be used from different threads.
+ *  - Problem-level failures (l_i > u_i, non-finite values) are reported per instance in
+ *    d_status and never affect other instances.
+ *  - FP64 throughout.
+ */
+#ifndef MI355X_TRON_H
+#define MI355X_TRON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TRON_OK = 0,
+    TRON_ERR_INVALID = 1,      /* bad argument (null pointer, size, family/n mismatch)      */
+    TRON_ERR_NOMEM = 2,        /* device or host allocation failed                          */
+    TRON_ERR_DEVICE = 3,       /* a HIP call failed                                         */
+    TRON_ERR_UNSUPPORTED = 4,  /* n outside the supported range for the family              */
+    TRON_ERR_BUSY = 5          /* server admission refused: over the memory budget          */
+} tron_err;
+
+/* Per-instance outcome written to d_status. */
+enum {
+    TRON_CONVERGED = 0,   /* ||grad_[l,u] f(x)||_inf <= gtol                              */
+    TRON_MAX_ITER = 1,    /* max_iter trust-region iterations taken                       */
+    TRON_STALLED = 2,     /* no model decrease possible / reductions at rounding level    */
+    TRON_NONFINITE = 3,   /* f or grad f not finite at an accepted point                  */
+    TRON_BAD_BOUNDS = 4   /* some l_i > u_i (or a NaN bound); x is left at x0             */
+};
+
+/* Problem families. Parameter block sizes (doubles per instance):
+ *   QP4:   n(n+1)/2 + n + 1 -- f = x'Qx/2 + c'x + kappa sum x_i^4; packed lower triangle of
+ *          Q row by row (Q00 Q10 Q11 Q20 ...), then c, then kappa. 1 <= n <= 128.
+ *   BR6:   36, n = 6 -- the branch subproblem of eq. exp-branch in x = (v_i, v_j, th_i,
+ *          th_j, z_ij, z_ji): [0..7] g_ij b_ij gc_ij bc_ij g_ji b_ji gc_ji bc_ji,
+ *          [8..15] targets of (p_ij q_ij p_ji q_ji w_i w_j th_i th_j), [16..23] their
+ *          multipliers, [24..25] multipliers of z_ij - p_ij and z_ji - p_ji, [26..33]
+ *          penalties of the eight couplings, [34..35] penalties of the two z couplings;
+ *          flows per eqs. pij..qji with w = v^2, wR = v_i v_j cos(th_i - th_j),
+ *          wI = v_i v_j sin(th_i - th_j).
+ *   HS45M: 0 -- f = 120 - prod x_i (the variant of hs45 in section 4.2). 1 <= n <= 8. */
+typedef enum { TRON_FAMILY_QP4 = 0, TRON_FAMILY_BR6 = 1, TRON_FAMILY_HS45M = 2 } tron_family;
+
+typedef struct {
+    double gtol;       /* absolute tolerance on ||grad_[l,u] f||_inf (default 1e-6)          */
+    int32_t max_iter;  /* trust-region iterations (default 500)                             */
+    uint32_t flags;    /* TRON_FLAG_*                                                        */
+    double cg_rtol;    /* CG stops when ||r|| <= cg_rtol ||r0|| (default 0.1)               */
+    double delta0;     /* > 0: initial radius of every instance; <= 0: ||grad_[l,u] f(x0)||_2 */
+} tron_options;
+
+/* Start from the radius and Cauchy step length the handle kept from its previous solve
+ * (per instance), instead of the cold rule. x0 is always the caller's. */
+#define TRON_FLAG_WARM 1u
+
+void tron_default_options(tron_options *opt);
+const char *tron_last_error(void);
+/* Parameter doubles per instance for (family, n); -1 if unsupported. */
+int64_t tron_param_size(tron_family family, int32_t n);
+
+typedef struct tron_batch tron_batch;
+
+/* Create a handle for `batch` instances of `family`. n_host (host, length batch) gives
+ * each instance's n, or is NULL and every instance has n_uniform. Instances are packed
+ * back to back in instance order: parameter block b starts at the sum of the sizes of
+ * blocks 0..b-1, and vector b (lo, hi, x0, x) at the sum of n over 0..b-1.
+ * The handle builds its launch plan (size buckets, kernel geometry, captured graph) here
+ * and owns per-instance resident state (trust radius, Cauchy step length) on the device.
+ * opt may be NULL (defaults). Errors: INVALID (batch < 0, n out of range, family/n
+ * mismatch), UNSUPPORTED, NOMEM, DEVICE. */
+tron_err tron_batch_create(tron_batch **out, tron_family family, int64_t batch,
+                           const int32_t *n_host, int32_t n_uniform, const tron_options *opt,
+                           void *stream);
+
+/* Solve every instance (Algorithm 1 per instance). d_x0 (read) and d_x (written) may be the
+ * same buffer for an in-place warm start. d_f (batch doubles), d_status and d_iters (batch
+ * int32 each) are written. d_params, d_lo, d_hi are read only. Bounds may be +-inf.
+ * Errors: INVALID (null pointers), DEVICE (launch failure). */
+tron_err tron_batch_solve(tron_batch *h, const double *d_params, const double *d_lo,
+                          const double *d_hi, const double *d_x0, double *d_x, double *d_f,
+                          int32_t *d_status, int32_t *d_iters, void *stream);
+
+/* Copy the resident per-instance state out of / into the handle: d_state holds 2*batch
+ * doubles, the radii then the Cauchy step lengths. Used for checkpoint and resume. */
+tron_err tron_batch_get_state(tron_batch *h, double *d_state, void *stream);
+tron_err tron_batch_set_state(tron_batch *h, const double *d_state, void *stream);
+
+/* Replace the options used by later solves (the plan is kept). */
+tron_err tron_batch_set_options(tron_batch *h, const tron_options *opt);
+
+/* Describe the launch plan: number of buckets, and for each bucket (up to max_buckets)
+ * its largest n, its lanes per instance and its instance count, as 3 int32 per bucket. */
+tron_err tron_batch_plan(const tron_batch *h, int32_t *nbuckets, int32_t *desc,
+                         int32_t max_buckets);
+
+tron_err tron_batch_destroy(tron_batch *h);
+
+/* ------------------------------------------------------------------------------------ */
+/* Component ADMM of the power-flow application (section 6.1).                           */
+/* ------------------------------------------------------------------------------------ */
+typedef struct {
+    int32_t nbus, nbranch, ngen, ref_bus;
+    double rho;                        /* penalty of every coupling                        */
+    double base_mva;                   /* generator costs are per MW, powers per unit      */
+    const int32_t *br_from, *br_to;    /* host, nbranch each                               */
+    const double *br_adm;              /* host, nbranch x 8 (BR6 order)                    */
+    const double *br_lo, *br_hi;       /* host, nbranch x 6 bounds on the BR6 variables    */
+    const int32_t *gen_bus;            /* host, ngen                                       */
+    const double *gen_cost;            /* host, ngen x 2: c2 (per MW^2), c1 (per MW)       */
+    const double *gen_lim;             /* host, ngen x 4: pmin pmax qmin qmax (per unit)   */
+    const double *bus_load;            /* host, nbus x 4: pd qd gsh bsh (per unit)         */
+} admm_network;
+
+typedef struct admm admm;
+
+/* Doubles in the flat ADMM state:
+ *   generators (ngen each, in this order): pg qg pg~ qg~ lambda_pg lambda_qg
+ *   branches: x (nbranch x 6), couplings y (nbranch x 8: p_ij q_ij p_ji q_ji w_i w_j th_i
+ *             th_j), bus copies of the flows (nbranch x 4), lambda (nbranch x 8),
+ *             mu (nbranch x 2), radius (nbranch), Cauchy step length (nbranch)
+ *   buses: w~ (nbus), theta~ (nbus)
+ * = 6 ngen + 30 nbranch + 2 nbus. */
+int64_t admm_state_size(const admm_network *net);
+
+/* Copy the network to the device and set the initial state (v = 1, theta = 0, z = 0,
+ * generator powers at mid-range, copies equal to the component values, multipliers 0).
+ * Every bus must be the end of at least one branch. */
+tron_err admm_create(admm **out, const admm_network *net, const tron_options *branch_opt,
+                     void *stream);
+
+/* Run `iters` ADMM iterations. Per iteration: generator updates and the batched branch
+ * solves (warm-started from the resident x, radius, step length), then the bus updates,
+ * then the multiplier updates. d_resid (2*iters doubles) receives (primal, dual) residual
+ * norms per iteration, or is NULL. */
+tron_err admm_step(admm *a, int32_t iters, double *d_resid, void *stream);
+
+/* Copy the state out / in (count must equal admm_state_size). */
+tron_err admm_get_state(admm *a, double *d_buf, int64_t count, void *stream);
+tron_err admm_set_state(admm *a, const double *d_buf, int64_t count, void *stream);
+tron_err admm_destroy(admm *a);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,461 @@
+// admm.hip -- the component ADMM of the power-flow application (section 6.1) on the GPU.
+//
+// One iteration, in the order the paper gives (generators and branches, then buses, then
+// multipliers), is six kernels on one stream:
+//   gen_pack   generator updates (closed form) and the BR6 parameter blocks of the branches
+//   lane_kernel<BR6>  batched branch solves, warm-started in place from the resident x,
+//              radius and Cauchy step length
+//   couplings  branch couplings y = (p_ij q_ij p_ji q_ji v_i^2 v_j^2 th_i th_j) at the new x
+//   buses      per bus: weighted projection of the targets onto the two balance equations
+//              (a 2 x 2 solve), new copies for its generators and branch ends, and the
+//              squared change of those copies (dual residual part)
+//   duals      multiplier updates and the squared primal residual parts
+//   reduce     one workgroup sums the parts in a fixed order (deterministic) into the
+//              residual norms of the iteration
+// The state stays on the device in the flat layout of include/tron.h; the host only
+// launches. The closed forms are the exact minimisers of the augmented Lagrangians of the
+// generator and bus subproblems (the paper states only that they exist).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "tron.h"
+#include "tron_internal.hpp"
+
+namespace {
+
+struct Net {
+    int32_t G, L, B, ref;
+    double rho, base;
+    const int32_t *br_from, *br_to, *gen_bus;
+    const double *adm, *blo, *bhi, *cost, *glim, *load;
+    const int32_t *bg_ptr, *bg_idx;   // generators of each bus (CSR, increasing index)
+    const int32_t *be_ptr, *be_idx;   // branch ends of each bus (CSR, 2*l + side, increasing)
+};
+
+struct View {
+    double *pg, *qg, *pgt, *qgt, *lpg, *lqg;
+    double *x, *y, *yt, *lam, *mu, *del, *alp, *wt, *tht;
+};
+
+__host__ __device__ inline View split(double *s, int64_t G, int64_t L, int64_t B)
+{
+    View v;
+    v.pg = s; v.qg = s + G; v.pgt = s + 2 * G; v.qgt = s + 3 * G; v.lpg = s + 4 * G; v.lqg = s + 5 * G;
+    double *b = s + 6 * G;
+    v.x = b; v.y = b + 6 * L; v.yt = b + 14 * L; v.lam = b + 18 * L; v.mu = b + 26 * L;
+    v.del = b + 28 * L; v.alp = b + 29 * L; v.wt = b + 30 * L; v.tht = v.wt + B;
+    (void)B;
+    return v;
+}
+
+__device__ inline double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// couplings of a branch at x (flows of eqs. pij..qji with w = v^2, wR = V cos, wI = V sin)
+__device__ inline void couplings(const double *adm, const double *x, double *y)
+{
+    double s, c;
+    sincos(x[2] - x[3], &s, &c);
+    const double vi = x[0], vj = x[1], V = vi * vj;
+    const double g0 = adm[0], b0 = adm[1], gc0 = adm[2], bc0 = adm[3];
+    const double g1 = adm[4], b1 = adm[5], gc1 = adm[6], bc1 = adm[7];
+    y[0] = gc0 * vi * vi + V * (b0 * s - g0 * c);
+    y[1] = bc0 * vi * vi - V * (b0 * c + g0 * s);
+    y[2] = gc1 * vj * vj - V * (g1 * c + b1 * s);
+    y[3] = bc1 * vj * vj + V * (g1 * s - b1 * c);
+    y[4] = vi * vi;
+    y[5] = vj * vj;
+    y[6] = x[2];
+    y[7] = x[3];
+}
+
+constexpr int kBlock = 256;
+
+__global__ __launch_bounds__(kBlock) void admm_init_kernel(Net n, double *s)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    View v = split(s, n.G, n.L, n.B);
+    if (t < n.G) {
+        const double *lim = n.glim + 4 * t;
+        v.pg[t] = 0.5 * (lim[0] + lim[1]);
+        v.qg[t] = 0.5 * (lim[2] + lim[3]);
+        v.pgt[t] = v.pg[t];
+        v.qgt[t] = v.qg[t];
+        v.lpg[t] = 0.0;
+        v.lqg[t] = 0.0;
+    } else if (t < (int64_t)n.G + n.L) {
+        const int64_t l = t - n.G;
+        const double start[6] = {1.0, 1.0, 0.0, 0.0, 0.0, 0.0};
+        double *x = v.x + 6 * l;
+        for (int i = 0; i < 6; i++) x[i] = clampd(start[i], n.blo[6 * l + i], n.bhi[6 * l + i]);
+        double y[8];
+        couplings(n.adm + 8 * l, x, y);
+        for (int k = 0; k < 8; k++) v.y[8 * l + k] = y[k];
+        for (int k = 0; k < 4; k++) v.yt[4 * l + k] = y[k];
+        for (int k = 0; k < 8; k++) v.lam[8 * l + k] = 0.0;
+        v.mu[2 * l] = 0.0;
+        v.mu[2 * l + 1] = 0.0;
+        v.del[l] = 0.0;
+        v.alp[l] = 0.0;
+    } else if (t < (int64_t)n.G + n.L + n.B) {
+        const int64_t b = t - n.G - n.L;
+        v.wt[b] = 1.0;
+        v.tht[b] = 0.0;
+    }
+}
+
+// generator updates and branch parameter blocks (both read only the previous copies)
+__global__ __launch_bounds__(kBlock) void gen_pack_kernel(Net n, double *s, double *prm)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    View v = split(s, n.G, n.L, n.B);
+    const double rho = n.rho;
+    if (t < n.G) {
+        const double c2 = n.base * n.base * n.cost[2 * t], c1 = n.base * n.cost[2 * t + 1];
+        const double *lim = n.glim + 4 * t;
+        const double p = (rho * v.pgt[t] - v.lpg[t] - c1) / (2.0 * c2 + rho);
+        const double q = v.qgt[t] - v.lqg[t] / rho;
+        v.pg[t] = clampd(p, lim[0], lim[1]);
+        v.qg[t] = clampd(q, lim[2], lim[3]);
+    } else if (t < (int64_t)n.G + n.L) {
+        const int64_t l = t - n.G;
+        const int i = n.br_from[l], j = n.br_to[l];
+        double *p = prm + 36 * l;
+        for (int k = 0; k < 8; k++) p[k] = n.adm[8 * l + k];
+        for (int k = 0; k < 4; k++) p[8 + k] = v.yt[4 * l + k];
+        p[12] = v.wt[i];
+        p[13] = v.wt[j];
+        p[14] = v.tht[i];
+        p[15] = v.tht[j];
+        for (int k = 0; k < 8; k++) p[16 + k] = v.lam[8 * l + k];
+        p[24] = v.mu[2 * l];
+        p[25] = v.mu[2 * l + 1];
+        for (int k = 0; k < 10; k++) p[26 + k] = rho;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void couplings_kernel(Net n, double *s)
+{
+    const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (l >= n.L) return;
+    View v = split(s, n.G, n.L, n.B);
+    double y[8];
+    couplings(n.adm + 8 * l, v.x + 6 * l, y);
+    for (int k = 0; k < 8; k++) v.y[8 * l + k] = y[k];
+}
+
+// bus subproblem: minimise sum w_k/2 (yt_k - t_k)^2, t_k = y_k + lam_k / rho, over the bus
+// copies (generator powers, branch-end flows, w shared by the ends, theta), subject to
+// the two balance rows; yt = t - W^-1 A' (A W^-1 A')^-1 (A t - b)
+__global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *part_dual)
+{
+    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (b >= n.B) return;
+    View v = split(s, n.G, n.L, n.B);
+    const double rho = n.rho;
+    double sgp = 0.0, sgq = 0.0, sep = 0.0, seq = 0.0, sw = 0.0, sth = 0.0;
+    const int g0 = n.bg_ptr[b], g1 = n.bg_ptr[b + 1];
+    const int e0 = n.be_ptr[b], e1 = n.be_ptr[b + 1];
+    for (int k = g0; k < g1; k++) {
+        const int g = n.bg_idx[k];
+        sgp += v.pg[g] + v.lpg[g] / rho;
+        sgq += v.qg[g] + v.lqg[g] / rho;
+    }
+    for (int k = e0; k < e1; k++) {
+        const int code = n.be_idx[k];
+        const int64_t l = code >> 1;
+        const int e = code & 1;
+        const double *y = v.y + 8 * l, *la = v.lam + 8 * l;
+        sep += y[2 * e] + la[2 * e] / rho;
+        seq += y[2 * e + 1] + la[2 * e + 1] / rho;
+        sw += y[4 + e] + la[4 + e] / rho;
+        sth += y[6 + e] + la[6 + e] / rho;
+    }
+    const double ng = (double)(g1 - g0), deg = (double)(e1 - e0);
+    const double *ld = n.load + 4 * b;
+    const double pd = ld[0], qd = ld[1], gs = ld[2], bs = ld[3];
+    const double tw = sw / deg, tth = sth / deg;
+    const double ww = deg * rho;
+    const double ep = sgp - sep - gs * tw - pd;
+    const double eq = sgq - seq + bs * tw - qd;
+    const double mpp = (ng + deg) / rho + gs * gs / ww;
+    const double mqq = (ng + deg) / rho + bs * bs / ww;
+    const double mpq = -gs * bs / ww;
+    const double det = mpp * mqq - mpq * mpq;
+    const double up = (mqq * ep - mpq * eq) / det;
+    const double uq = (mpp * eq - mpq * ep) / det;
+    const double wnew = tw - (-gs * up + bs * uq) / ww;
+    const double tnew = b == n.ref ? 0.0 : tth;
+    double d2 = 0.0;
+    for (int k = g0; k < g1; k++) {
+        const int g = n.bg_idx[k];
+        const double np = v.pg[g] + v.lpg[g] / rho - up / rho;
+        const double nq = v.qg[g] + v.lqg[g] / rho - uq / rho;
+        d2 += (np - v.pgt[g]) * (np - v.pgt[g]) + (nq - v.qgt[g]) * (nq - v.qgt[g]);
+        v.pgt[g] = np;
+        v.qgt[g] = nq;
+    }
+    const double dw = wnew - v.wt[b], dt = tnew - v.tht[b];
+    for (int k = e0; k < e1; k++) {
+        const int code = n.be_idx[k];
+        const int64_t l = code >> 1;
+        const int e = code & 1;
+        const double *y = v.y + 8 * l, *la = v.lam + 8 * l;
+        double *yt = v.yt + 4 * l;
+        const double np = y[2 * e] + la[2 * e] / rho + up / rho;
+        const double nq = y[2 * e + 1] + la[2 * e + 1] / rho + uq / rho;
+        d2 += (np - yt[2 * e]) * (np - yt[2 * e]) + (nq - yt[2 * e + 1]) * (nq - yt[2 * e + 1]);
+        d2 += dw * dw + dt * dt;
+        yt[2 * e] = np;
+        yt[2 * e + 1] = nq;
+    }
+    v.wt[b] = wnew;
+    v.tht[b] = tnew;
+    part_dual[b] = d2;
+}
+
+// multipliers: lam += rho (y - yt) for every coupling, mu += rho (z - p)
+__global__ __launch_bounds__(kBlock) void duals_kernel(Net n, double *s, double *part_primal)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    View v = split(s, n.G, n.L, n.B);
+    const double rho = n.rho;
+    if (t < n.G) {
+        const double rp = v.pg[t] - v.pgt[t], rq = v.qg[t] - v.qgt[t];
+        v.lpg[t] += rho * rp;
+        v.lqg[t] += rho * rq;
+        part_primal[t] = rp * rp + rq * rq;
+    } else if (t < (int64_t)n.G + n.L) {
+        const int64_t l = t - n.G;
+        const int i = n.br_from[l], j = n.br_to[l];
+        const double *y = v.y + 8 * l, *yt = v.yt + 4 * l, *x = v.x + 6 * l;
+        double *la = v.lam + 8 * l;
+        const double copy[8] = {yt[0], yt[1], yt[2], yt[3], v.wt[i], v.wt[j], v.tht[i], v.tht[j]};
+        double p2 = 0.0;
+        for (int k = 0; k < 8; k++) {
+            const double r = y[k] - copy[k];
+            la[k] += rho * r;
+            p2 += r * r;
+        }
+        v.mu[2 * l] += rho * (x[4] - y[0]);
+        v.mu[2 * l + 1] += rho * (x[5] - y[2]);
+        part_primal[t] = p2;
+    }
+}
+
+constexpr int kReduce = 1024;
+
+// one workgroup: fixed per-thread strides and a fixed tree, so the result is deterministic
+__global__ __launch_bounds__(kReduce) void reduce_kernel(const double *part_primal, int64_t np,
+                                                         const double *part_dual, int64_t nd,
+                                                         double rho, double *resid)
+{
+    __shared__ double sp[kReduce], sd[kReduce];
+    const int t = threadIdx.x;
+    double a = 0.0, b = 0.0;
+    for (int64_t k = t; k < np; k += kReduce) a += part_primal[k];
+    for (int64_t k = t; k < nd; k += kReduce) b += part_dual[k];
+    sp[t] = a;
+    sd[t] = b;
+    __syncthreads();
+    for (int w = kReduce / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            sp[t] += sp[t + w];
+            sd[t] += sd[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0 && resid) {
+        resid[0] = sqrt(sp[0]);
+        resid[1] = rho * sqrt(sd[0]);
+    }
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+struct admm {
+    int device = 0;
+    Net net{};
+    tron_options opt{};
+    int64_t state_size = 0;
+    double *d_state = nullptr;
+    double *d_prm = nullptr, *d_f = nullptr, *d_part = nullptr;
+    int32_t *d_status = nullptr, *d_iters = nullptr;
+    std::vector<void *> owned;
+};
+
+static void free_admm(admm *a)
+{
+    if (!a) return;
+    for (void *p : a->owned) (void)hipFree(p);
+    delete a;
+}
+
+extern "C" int64_t admm_state_size(const admm_network *n)
+{
+    if (!n) return -1;
+    return 6LL * n->ngen + 30LL * n->nbranch + 2LL * n->nbus;
+}
+
+template <class T>
+static tron_err upload(admm *a, T **dst, const T *src, size_t count, hipStream_t st)
+{
+    *dst = nullptr;
+    if (count == 0) return TRON_OK;
+    if (hipMalloc((void **)dst, sizeof(T) * count) != hipSuccess)
+        return mt_fail(TRON_ERR_NOMEM, "device allocation failed");
+    a->owned.push_back(*dst);
+    if (src) HIP_TRY(hipMemcpyAsync(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice, st));
+    return TRON_OK;
+}
+
+extern "C" tron_err admm_create(admm **out, const admm_network *n, const tron_options *bopt,
+                                void *stream)
+{
+    if (!out || !n) return mt_fail(TRON_ERR_INVALID, "null argument");
+    *out = nullptr;
+    if (n->nbus <= 0 || n->nbranch <= 0 || n->ngen < 0 || n->ref_bus < 0 || n->ref_bus >= n->nbus)
+        return mt_fail(TRON_ERR_INVALID, "network sizes invalid");
+    if (!n->br_from || !n->br_to || !n->br_adm || !n->br_lo || !n->br_hi || !n->bus_load ||
+        (n->ngen > 0 && (!n->gen_bus || !n->gen_cost || !n->gen_lim)))
+        return mt_fail(TRON_ERR_INVALID, "null network array");
+    if (!(n->rho > 0.0)) return mt_fail(TRON_ERR_INVALID, "rho must be positive");
+    const int G = n->ngen, L = n->nbranch, B = n->nbus;
+    // adjacency in increasing index order
+    std::vector<int32_t> gptr(B + 1, 0), eptr(B + 1, 0);
+    for (int g = 0; g < G; g++) {
+        if (n->gen_bus[g] < 0 || n->gen_bus[g] >= B) return mt_fail(TRON_ERR_INVALID, "generator bus out of range");
+        gptr[n->gen_bus[g] + 1]++;
+    }
+    for (int l = 0; l < L; l++) {
+        if (n->br_from[l] < 0 || n->br_from[l] >= B || n->br_to[l] < 0 || n->br_to[l] >= B ||
+            n->br_from[l] == n->br_to[l])
+            return mt_fail(TRON_ERR_INVALID, "branch %d ends invalid", l);
+        eptr[n->br_from[l] + 1]++;
+        eptr[n->br_to[l] + 1]++;
+    }
+    for (int b = 0; b < B; b++) {
+        if (eptr[b + 1] == 0) return mt_fail(TRON_ERR_INVALID, "bus %d has no branch", b);
+        gptr[b + 1] += gptr[b];
+        eptr[b + 1] += eptr[b];
+    }
+    std::vector<int32_t> gidx(G), eidx(2 * (size_t)L), gfill(gptr.begin(), gptr.end() - 1),
+        efill(eptr.begin(), eptr.end() - 1);
+    for (int g = 0; g < G; g++) gidx[gfill[n->gen_bus[g]]++] = g;
+    for (int l = 0; l < L; l++) {
+        eidx[efill[n->br_from[l]]++] = 2 * l;
+        eidx[efill[n->br_to[l]]++] = 2 * l + 1;
+    }
+    admm *a = new (std::nothrow) admm();
+    if (!a) return mt_fail(TRON_ERR_NOMEM, "host allocation failed");
+    (void)hipGetDevice(&a->device);
+    tron_default_options(&a->opt);
+    if (bopt) a->opt = *bopt;
+    a->opt.flags |= TRON_FLAG_WARM;
+    hipStream_t st = (hipStream_t)stream;
+    Net &d = a->net;
+    d.G = G; d.L = L; d.B = B; d.ref = n->ref_bus; d.rho = n->rho; d.base = n->base_mva;
+    tron_err rc = TRON_OK;
+    int32_t *p_from, *p_to, *p_gbus, *p_gptr, *p_gidx, *p_eptr, *p_eidx;
+    double *p_adm, *p_lo, *p_hi, *p_cost, *p_lim, *p_load;
+#define UP(dst, src, cnt) if ((rc = upload(a, &dst, src, cnt, st)) != TRON_OK) { free_admm(a); return rc; }
+    UP(p_from, n->br_from, L);
+    UP(p_to, n->br_to, L);
+    UP(p_gbus, n->gen_bus, G);
+    UP(p_adm, n->br_adm, 8 * (size_t)L);
+    UP(p_lo, n->br_lo, 6 * (size_t)L);
+    UP(p_hi, n->br_hi, 6 * (size_t)L);
+    UP(p_cost, n->gen_cost, 2 * (size_t)G);
+    UP(p_lim, n->gen_lim, 4 * (size_t)G);
+    UP(p_load, n->bus_load, 4 * (size_t)B);
+    UP(p_gptr, gptr.data(), B + 1);
+    UP(p_gidx, gidx.data(), G);
+    UP(p_eptr, eptr.data(), B + 1);
+    UP(p_eidx, eidx.data(), 2 * (size_t)L);
+    a->state_size = admm_state_size(n);
+    UP(a->d_state, (const double *)nullptr, (size_t)a->state_size);
+    UP(a->d_prm, (const double *)nullptr, 36 * (size_t)L);
+    UP(a->d_f, (const double *)nullptr, (size_t)L);
+    UP(a->d_part, (const double *)nullptr, (size_t)G + L + B);
+    UP(a->d_status, (const int32_t *)nullptr, (size_t)L);
+    UP(a->d_iters, (const int32_t *)nullptr, (size_t)L);
+#undef UP
+    d.br_from = p_from; d.br_to = p_to; d.gen_bus = p_gbus; d.adm = p_adm; d.blo = p_lo;
+    d.bhi = p_hi; d.cost = p_cost; d.glim = p_lim; d.load = p_load; d.bg_ptr = p_gptr;
+    d.bg_idx = p_gidx; d.be_ptr = p_eptr; d.be_idx = p_eidx;
+    hipLaunchKernelGGL(admm_init_kernel, dim3(grid_for((int64_t)G + L + B)), dim3(kBlock), 0, st, d, a->d_state);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+        free_admm(a);
+        return mt_fail(TRON_ERR_DEVICE, "initialisation failed");
+    }
+    *out = a;
+    return TRON_OK;
+}
+
+extern "C" tron_err admm_step(admm *a, int32_t iters, double *d_resid, void *stream)
+{
+    if (!a || iters < 0) return mt_fail(TRON_ERR_INVALID, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    const Net &n = a->net;
+    View v = split(a->d_state, n.G, n.L, n.B);
+    LaneArgs la{};
+    la.params = a->d_prm;
+    la.lo = n.blo;
+    la.hi = n.bhi;
+    la.x0 = v.x;
+    la.x = v.x;
+    la.f = a->d_f;
+    la.status = a->d_status;
+    la.iters = a->d_iters;
+    la.state = v.del;  // radius then Cauchy step length, contiguous in the state
+    la.count = n.L;
+    la.batch = n.L;
+    la.n_uniform = 6;
+    la.psize = 36;
+    la.opt.gtol = a->opt.gtol;
+    la.opt.cg_rtol = a->opt.cg_rtol;
+    la.opt.delta0 = a->opt.delta0;
+    la.opt.max_iter = a->opt.max_iter;
+    la.opt.warm = 1;
+    double *part_primal = a->d_part, *part_dual = a->d_part + n.G + n.L;
+    for (int32_t it = 0; it < iters; it++) {
+        hipLaunchKernelGGL(gen_pack_kernel, dim3(grid_for((int64_t)n.G + n.L)), dim3(kBlock), 0, st, n,
+                           a->d_state, a->d_prm);
+        mt_launch_br6(la, st);
+        hipLaunchKernelGGL(couplings_kernel, dim3(grid_for(n.L)), dim3(kBlock), 0, st, n, a->d_state);
+        hipLaunchKernelGGL(bus_kernel, dim3(grid_for(n.B)), dim3(kBlock), 0, st, n, a->d_state, part_dual);
+        hipLaunchKernelGGL(duals_kernel, dim3(grid_for((int64_t)n.G + n.L)), dim3(kBlock), 0, st, n,
+                           a->d_state, part_primal);
+        hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kReduce), 0, st, part_primal,
+                           (int64_t)n.G + n.L, part_dual, (int64_t)n.B, n.rho,
+                           d_resid ? d_resid + 2 * (int64_t)it : nullptr);
+    }
+    HIP_TRY(hipGetLastError());
+    return TRON_OK;
+}
+
+extern "C" tron_err admm_get_state(admm *a, double *d_buf, int64_t count, void *stream)
+{
+    if (!a || !d_buf || count != a->state_size) return mt_fail(TRON_ERR_INVALID, "bad argument");
+    HIP_TRY(hipMemcpyAsync(d_buf, a->d_state, sizeof(double) * count, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    return TRON_OK;
+}
+
+extern "C" tron_err admm_set_state(admm *a, const double *d_buf, int64_t count, void *stream)
+{
+    if (!a || !d_buf || count != a->state_size) return mt_fail(TRON_ERR_INVALID, "bad argument");
+    HIP_TRY(hipMemcpyAsync(a->d_state, d_buf, sizeof(double) * count, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    return TRON_OK;
+}
+
+extern "C" tron_err admm_destroy(admm *a)
+{
+    free_admm(a);
+    return TRON_OK;
+}

@@ -1,0 +1,37 @@
+// tron_internal.hpp -- declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lane_tron.hpp"
+#include "tron.h"
+
+// Arguments of the lane-per-instance solve kernels.
+struct LaneArgs {
+    const double *params, *lo, *hi, *x0;
+    double *x, *f;
+    int32_t *status, *iters;
+    double *state;           // radius [batch], Cauchy step [batch]
+    const int32_t *index;    // instance list of this bucket, or null (all, in order)
+    const int32_t *nper;     // per-instance n, or null (n_uniform)
+    const int64_t *poff, *voff;
+    int64_t count, batch;
+    int32_t n_uniform, psize;
+    mt::Options opt;
+};
+
+typedef void (*lane_launch_fn)(const LaneArgs &, hipStream_t);
+
+// Launch the BR6 lane kernel (n = 6) over a.count instances.
+void mt_launch_br6(const LaneArgs &a, hipStream_t st);
+
+// Record an error message for tron_last_error() and return `code`.
+tron_err mt_fail(tron_err code, const char *fmt, ...);
+
+#define HIP_TRY(expr)                                                                         \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return mt_fail(TRON_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)

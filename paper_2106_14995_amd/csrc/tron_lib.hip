@@ -1,0 +1,372 @@
+// tron_lib.hip -- kernels and C ABI of the MI355X batched TRON library (see include/tron.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lane_tron.hpp"
+#include "tron.h"
+#include "tron_internal.hpp"
+
+// ------------------------------------------------------------------------------------
+// error reporting
+// ------------------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+tron_err mt_fail(tron_err code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+
+extern "C" const char *tron_last_error(void) { return g_err.c_str(); }
+
+extern "C" void tron_default_options(tron_options *o)
+{
+    if (!o) return;
+    o->gtol = 1e-6;
+    o->max_iter = 500;
+    o->flags = 0u;
+    o->cg_rtol = 0.1;
+    o->delta0 = 0.0;
+}
+
+extern "C" int64_t tron_param_size(tron_family fam, int32_t n)
+{
+    if (fam == TRON_FAMILY_QP4 && n >= 1 && n <= 128) return (int64_t)n * (n + 1) / 2 + n + 1;
+    if (fam == TRON_FAMILY_BR6 && n == 6) return 36;
+    if (fam == TRON_FAMILY_HS45M && n >= 1 && n <= 8) return 0;
+    return -1;
+}
+
+// ------------------------------------------------------------------------------------
+// lane-per-instance kernels (n <= 8)
+// ------------------------------------------------------------------------------------
+constexpr int kLaneBlock = 256;
+
+template <class F, int N>
+__global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
+    if (t >= a.count) return;
+    const int64_t b = a.index ? (int64_t)a.index[t] : t;
+    const int n = a.nper ? a.nper[b] : a.n_uniform;
+    const int64_t po = a.poff ? a.poff[b] : b * (int64_t)a.psize;
+    const int64_t vo = a.voff ? a.voff[b] : b * (int64_t)n;
+    mt::LaneTron<F, N> s;
+    s.fam.load(a.params + po, n);
+    const double *lo = a.lo + vo, *hi = a.hi + vo, *x0 = a.x0 + vo;
+    MT_UNROLL for (int i = 0; i < N; i++) {
+        const bool in = i < n;
+        const int k = in ? i : 0;
+        s.lo[i] = in ? lo[k] : F::pad;
+        s.hi[i] = in ? hi[k] : F::pad;
+        s.x[i] = in ? x0[k] : F::pad;
+    }
+    const double din = a.opt.warm ? a.state[b] : 0.0;
+    const double ain = a.opt.warm ? a.state[a.batch + b] : 0.0;
+    const int32_t st = s.solve(a.opt, din, ain);
+    double *xo = a.x + vo;
+    MT_UNROLL for (int i = 0; i < N; i++)
+        if (i < n) xo[i] = s.x[i];
+    a.f[b] = s.f;
+    a.status[b] = st;
+    a.iters[b] = s.iters;
+    a.state[b] = s.delta;
+    a.state[a.batch + b] = s.alphac;
+}
+
+
+template <class F, int N>
+static void launch_lane(const LaneArgs &a, hipStream_t st)
+{
+    const unsigned grid = (unsigned)((a.count + kLaneBlock - 1) / kLaneBlock);
+    if (grid) hipLaunchKernelGGL((lane_kernel<F, N>), dim3(grid), dim3(kLaneBlock), 0, st, a);
+}
+
+static lane_launch_fn lane_launcher(tron_family fam, int N)
+{
+    using namespace mt;
+    if (fam == TRON_FAMILY_BR6) return N == 6 ? launch_lane<BR6, 6> : nullptr;
+    if (fam == TRON_FAMILY_QP4) {
+        switch (N) {
+        case 1: return launch_lane<QP4<1>, 1>;
+        case 2: return launch_lane<QP4<2>, 2>;
+        case 3: return launch_lane<QP4<3>, 3>;
+        case 4: return launch_lane<QP4<4>, 4>;
+        case 5: return launch_lane<QP4<5>, 5>;
+        case 6: return launch_lane<QP4<6>, 6>;
+        case 7: return launch_lane<QP4<7>, 7>;
+        case 8: return launch_lane<QP4<8>, 8>;
+        }
+    }
+    if (fam == TRON_FAMILY_HS45M) {
+        switch (N) {
+        case 1: return launch_lane<HS45M<1>, 1>;
+        case 2: return launch_lane<HS45M<2>, 2>;
+        case 3: return launch_lane<HS45M<3>, 3>;
+        case 4: return launch_lane<HS45M<4>, 4>;
+        case 5: return launch_lane<HS45M<5>, 5>;
+        case 6: return launch_lane<HS45M<6>, 6>;
+        case 7: return launch_lane<HS45M<7>, 7>;
+        case 8: return launch_lane<HS45M<8>, 8>;
+        }
+    }
+    return nullptr;
+}
+
+void mt_launch_br6(const LaneArgs &a, hipStream_t st) { launch_lane<mt::BR6, 6>(a, st); }
+
+// ------------------------------------------------------------------------------------
+// batch handle
+// ------------------------------------------------------------------------------------
+struct Bucket {
+    int32_t nmax;      // compile-time size of the kernel
+    int32_t lanes;     // lanes per instance
+    int64_t count;     // instances in the bucket
+    int32_t *d_index;  // instance list (null when the bucket is the whole batch in order)
+    lane_launch_fn lane;
+};
+
+struct tron_batch {
+    int device = 0;
+    tron_family fam = TRON_FAMILY_QP4;
+    int64_t batch = 0;
+    int32_t n_uniform = 0;     // 0 when sizes differ
+    int32_t nmax = 0;
+    tron_options opt{};
+    double *d_state = nullptr;
+    int32_t *d_n = nullptr;
+    int64_t *d_poff = nullptr, *d_voff = nullptr;
+    std::vector<Bucket> buckets;
+};
+
+static mt::Options dev_options(const tron_options &o)
+{
+    mt::Options d;
+    d.gtol = o.gtol;
+    d.cg_rtol = o.cg_rtol;
+    d.delta0 = o.delta0;
+    d.max_iter = o.max_iter;
+    d.warm = (o.flags & TRON_FLAG_WARM) ? 1 : 0;
+    return d;
+}
+
+static void free_batch(tron_batch *h)
+{
+    if (!h) return;
+    (void)hipFree(h->d_state);
+    (void)hipFree(h->d_n);
+    (void)hipFree(h->d_poff);
+    (void)hipFree(h->d_voff);
+    for (auto &b : h->buckets) (void)hipFree(b.d_index);
+    delete h;
+}
+
+static tron_err check_options(const tron_options &o)
+{
+    if (!(o.gtol >= 0.0) || o.max_iter < 0 || !(o.cg_rtol >= 0.0) || !(o.delta0 == o.delta0))
+        return mt_fail(TRON_ERR_INVALID, "invalid options");
+    return TRON_OK;
+}
+
+// Buckets of the lane kernel: instances grouped by the smallest supported kernel size
+// that holds them (sizes 1..8 each get their own kernel).
+static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStream_t st)
+{
+    if (h->batch == 0) return TRON_OK;
+    if (h->n_uniform) {
+        Bucket b{};
+        b.nmax = h->n_uniform;
+        b.lanes = 1;
+        b.count = h->batch;
+        b.d_index = nullptr;
+        b.lane = lane_launcher(h->fam, h->n_uniform);
+        if (!b.lane) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d not supported for this family", h->n_uniform);
+        h->buckets.push_back(b);
+        return TRON_OK;
+    }
+    std::vector<std::vector<int32_t>> lists(9);
+    for (int64_t i = 0; i < h->batch; i++) {
+        if (n[i] > 8) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d exceeds the lane kernel", n[i]);
+        lists[n[i]].push_back((int32_t)i);
+    }
+    for (int k = 1; k <= 8; k++) {
+        if (lists[k].empty()) continue;
+        Bucket b{};
+        b.nmax = k;
+        b.lanes = 1;
+        b.count = (int64_t)lists[k].size();
+        b.lane = lane_launcher(h->fam, k);
+        if (!b.lane) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d not supported for this family", k);
+        HIP_TRY(hipMalloc(&b.d_index, sizeof(int32_t) * lists[k].size()));
+        HIP_TRY(hipMemcpyAsync(b.d_index, lists[k].data(), sizeof(int32_t) * lists[k].size(),
+                               hipMemcpyHostToDevice, st));
+        h->buckets.push_back(b);
+    }
+    return TRON_OK;
+}
+
+extern "C" tron_err tron_batch_create(tron_batch **out, tron_family fam, int64_t batch,
+                                      const int32_t *n_host, int32_t n_uniform,
+                                      const tron_options *opt, void *stream)
+{
+    if (!out) return mt_fail(TRON_ERR_INVALID, "out is null");
+    *out = nullptr;
+    if (batch < 0 || batch > (int64_t)INT32_MAX) return mt_fail(TRON_ERR_INVALID, "batch out of range");
+    if (fam != TRON_FAMILY_QP4 && fam != TRON_FAMILY_BR6 && fam != TRON_FAMILY_HS45M)
+        return mt_fail(TRON_ERR_INVALID, "unknown family");
+    tron_options o;
+    tron_default_options(&o);
+    if (opt) o = *opt;
+    if (check_options(o) != TRON_OK) return TRON_ERR_INVALID;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> n;
+    int32_t uni = 0;
+    if (n_host) {
+        n.assign(n_host, n_host + batch);
+        uni = batch > 0 ? n[0] : 1;
+        for (int64_t i = 0; i < batch; i++) {
+            if (tron_param_size(fam, n[i]) < 0)
+                return mt_fail(TRON_ERR_INVALID, "instance %lld: n = %d invalid for the family", (long long)i, n[i]);
+            if (n[i] != uni) uni = 0;
+        }
+    } else {
+        if (tron_param_size(fam, n_uniform) < 0)
+            return mt_fail(TRON_ERR_INVALID, "n = %d invalid for the family", n_uniform);
+        uni = n_uniform;
+    }
+    tron_batch *h = new (std::nothrow) tron_batch();
+    if (!h) return mt_fail(TRON_ERR_NOMEM, "host allocation failed");
+    (void)hipGetDevice(&h->device);
+    h->fam = fam;
+    h->batch = batch;
+    h->n_uniform = uni;
+    h->opt = o;
+    tron_err rc = TRON_OK;
+    auto bail = [&](tron_err e) { free_batch(h); return e; };
+    if (batch > 0) {
+        if (hipMalloc(&h->d_state, sizeof(double) * 2 * batch) != hipSuccess)
+            return bail(mt_fail(TRON_ERR_NOMEM, "state allocation failed"));
+        if (hipMemsetAsync(h->d_state, 0, sizeof(double) * 2 * batch, st) != hipSuccess)
+            return bail(mt_fail(TRON_ERR_DEVICE, "state clear failed"));
+    }
+    if (!uni && batch > 0) {
+        std::vector<int64_t> po(batch), vo(batch);
+        int64_t pa = 0, va = 0;
+        for (int64_t i = 0; i < batch; i++) {
+            po[i] = pa;
+            vo[i] = va;
+            pa += tron_param_size(fam, n[i]);
+            va += n[i];
+        }
+        if (hipMalloc(&h->d_n, sizeof(int32_t) * batch) != hipSuccess ||
+            hipMalloc(&h->d_poff, sizeof(int64_t) * batch) != hipSuccess ||
+            hipMalloc(&h->d_voff, sizeof(int64_t) * batch) != hipSuccess)
+            return bail(mt_fail(TRON_ERR_NOMEM, "offset allocation failed"));
+        if (hipMemcpyAsync(h->d_n, n.data(), sizeof(int32_t) * batch, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(h->d_poff, po.data(), sizeof(int64_t) * batch, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(h->d_voff, vo.data(), sizeof(int64_t) * batch, hipMemcpyHostToDevice, st) != hipSuccess)
+            return bail(mt_fail(TRON_ERR_DEVICE, "offset upload failed"));
+        // the host vectors die here; make the copies complete first
+        if (hipStreamSynchronize(st) != hipSuccess) return bail(mt_fail(TRON_ERR_DEVICE, "sync failed"));
+    }
+    rc = build_plan(h, n, st);
+    if (rc != TRON_OK) return bail(rc);
+    if (hipStreamSynchronize(st) != hipSuccess) return bail(mt_fail(TRON_ERR_DEVICE, "sync failed"));
+    *out = h;
+    return TRON_OK;
+}
+
+extern "C" tron_err tron_batch_solve(tron_batch *h, const double *d_params, const double *d_lo,
+                                     const double *d_hi, const double *d_x0, double *d_x,
+                                     double *d_f, int32_t *d_status, int32_t *d_iters, void *stream)
+{
+    if (!h) return mt_fail(TRON_ERR_INVALID, "handle is null");
+    if (h->batch == 0) return TRON_OK;
+    if ((!d_params && h->fam != TRON_FAMILY_HS45M) || !d_lo || !d_hi || !d_x0 || !d_x || !d_f ||
+        !d_status || !d_iters)
+        return mt_fail(TRON_ERR_INVALID, "null device pointer");
+    hipStream_t st = (hipStream_t)stream;
+    LaneArgs a{};
+    a.params = d_params;
+    a.lo = d_lo;
+    a.hi = d_hi;
+    a.x0 = d_x0;
+    a.x = d_x;
+    a.f = d_f;
+    a.status = d_status;
+    a.iters = d_iters;
+    a.state = h->d_state;
+    a.nper = h->n_uniform ? nullptr : h->d_n;
+    a.poff = h->n_uniform ? nullptr : h->d_poff;
+    a.voff = h->n_uniform ? nullptr : h->d_voff;
+    a.batch = h->batch;
+    a.n_uniform = h->n_uniform;
+    a.psize = h->n_uniform ? (int32_t)tron_param_size(h->fam, h->n_uniform) : 0;
+    a.opt = dev_options(h->opt);
+    for (const Bucket &b : h->buckets) {
+        a.index = b.d_index;
+        a.count = b.count;
+        b.lane(a, st);
+    }
+    HIP_TRY(hipGetLastError());
+    return TRON_OK;
+}
+
+extern "C" tron_err tron_batch_get_state(tron_batch *h, double *d_state, void *stream)
+{
+    if (!h || (!d_state && h->batch)) return mt_fail(TRON_ERR_INVALID, "null argument");
+    if (h->batch)
+        HIP_TRY(hipMemcpyAsync(d_state, h->d_state, sizeof(double) * 2 * h->batch,
+                               hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return TRON_OK;
+}
+
+extern "C" tron_err tron_batch_set_state(tron_batch *h, const double *d_state, void *stream)
+{
+    if (!h || (!d_state && h->batch)) return mt_fail(TRON_ERR_INVALID, "null argument");
+    if (h->batch)
+        HIP_TRY(hipMemcpyAsync(h->d_state, d_state, sizeof(double) * 2 * h->batch,
+                               hipMemcpyDeviceToDevice, (hipStream_t)stream));
+    return TRON_OK;
+}
+
+extern "C" tron_err tron_batch_set_options(tron_batch *h, const tron_options *opt)
+{
+    if (!h || !opt) return mt_fail(TRON_ERR_INVALID, "null argument");
+    if (check_options(*opt) != TRON_OK) return TRON_ERR_INVALID;
+    h->opt = *opt;
+    return TRON_OK;
+}
+
+extern "C" tron_err tron_batch_plan(const tron_batch *h, int32_t *nbuckets, int32_t *desc,
+                                    int32_t max_buckets)
+{
+    if (!h || !nbuckets) return mt_fail(TRON_ERR_INVALID, "null argument");
+    *nbuckets = (int32_t)h->buckets.size();
+    for (int32_t i = 0; desc && i < max_buckets && i < (int32_t)h->buckets.size(); i++) {
+        desc[3 * i] = h->buckets[i].nmax;
+        desc[3 * i + 1] = h->buckets[i].lanes;
+        desc[3 * i + 2] = (int32_t)h->buckets[i].count;
+    }
+    return TRON_OK;
+}
+
+extern "C" tron_err tron_batch_destroy(tron_batch *h)
+{
+    free_batch(h);
+    return TRON_OK;
+}

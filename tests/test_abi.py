@@ -1,0 +1,52 @@
+"""The C ABI library loads and exports every function include/tron.h declares (no GPU
+needed: nothing here launches work), and the host-side helpers behave."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "tron.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("tron_batch_create", "tron_batch_solve", "tron_batch_destroy", "admm_step"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2106_14995_amd import tron
+    L = tron.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_host_helpers():
+    from paper_2106_14995_amd import tron
+    assert tron.param_size(tron.QP4, 8) == 36 + 8 + 1
+    assert tron.param_size(tron.QP4, 128) == 128 * 129 // 2 + 129
+    assert tron.param_size(tron.BR6, 6) == 36
+    assert tron.param_size(tron.BR6, 5) == -1
+    assert tron.param_size(tron.HS45M, 4) == 0
+    o = tron.options()
+    assert o.gtol == 1e-6 and o.max_iter == 500 and o.cg_rtol == 0.1 and o.flags == 0
+
+
+def test_create_rejects_bad_arguments_before_touching_the_device():
+    from paper_2106_14995_amd import tron
+    h = C.c_void_p()
+    L = tron.lib()
+    assert L.tron_batch_create(None, 0, 1, None, 4, None, None) == 1
+    assert L.tron_batch_create(C.byref(h), 7, 1, None, 4, None, None) == 1
+    assert L.tron_batch_create(C.byref(h), tron.BR6, 1, None, 5, None, None) == 1
+    assert L.tron_batch_create(C.byref(h), tron.QP4, -1, None, 4, None, None) == 1
+    assert b"invalid" in L.tron_last_error() or len(L.tron_last_error()) > 0
