@@ -544,6 +544,8 @@ typedef struct {
     int *idx;                     /* free set                                             */
     double *A, *L;                /* m x m block of H and its factor                       */
     double *rF, *rh, *sh, *pp, *z, *yv, *qh, *tv, *wF;
+    int *lidx;                    /* free set of the last factored pass (L is its factor)  */
+    int lm;                       /* its size; 0 when no pass factored this iteration      */
     double fl;                    /* algorithmic flops                                     */
     int cauchy_trials, search_trials, passes, cg_iters, chol_tries;
 } ws_t;
@@ -682,6 +684,7 @@ static int pcg(ws_t *w, int m, double delta, double cg_rtol)
 static void subspace(ws_t *w, double delta, double cg_rtol)
 {
     int n = w->n;
+    w->lm = 0;
     for (int pass = 0; pass < n; pass++) {
         int m = 0;
         for (int i = 0; i < n; i++)
@@ -698,6 +701,8 @@ static void subspace(ws_t *w, double delta, double cg_rtol)
             for (int b = 0; b < m; b++) w->A[a * m + b] = w->H[w->idx[a] * n + w->idx[b]];
         }
         precond(w, m);
+        w->lm = m;
+        memcpy(w->lidx, w->idx, sizeof(int) * m);
         int ex = pcg(w, m, delta, cg_rtol);
         memcpy(w->wF, w->sh, sizeof(double) * m);
         trsv_bwd(m, w->L, w->wF, &w->fl);              /* w = L^-T s_hat */
@@ -726,6 +731,29 @@ static void subspace(ws_t *w, double delta, double cg_rtol)
         }
         if (!((ex == CG_CONVERGED || ex == CG_MAXIT) && newly_bound)) break;
     }
+}
+
+/* Length of the step s in the norm of the trust region that bounded it (reading S31): the
+ * conjugate-gradient step is bounded by ||L^T w|| <= delta (Algorithm 1 CG step), so on the
+ * free set of the last factored pass the step is measured as ||L^T s_F||, and outside it
+ * in the Euclidean norm. With no factored pass this is ||s||_2. */
+static double step_norm(ws_t *w)
+{
+    int n = w->n, m = w->lm;
+    if (m == 0) return nrm2(n, w->s, &w->fl);
+    double ss = 0.0;
+    for (int a = 0; a < m; a++) {
+        double t = 0.0;
+        for (int b = a; b < m; b++) t += w->L[b * m + a] * w->s[w->lidx[b]];
+        ss += t * t;
+    }
+    int k = 0;
+    for (int i = 0; i < n; i++) {
+        if (k < m && w->lidx[k] == i) { k++; continue; }
+        ss += w->s[i] * w->s[i];
+    }
+    w->fl += (double)m * (m + 1) + 2.0 * n + 1.0;
+    return sqrt(ss);
 }
 
 /* Radius update after a trial (reading S2, the interval rule of TRON). */
@@ -782,10 +810,10 @@ static int tron_one(int fam, int n, const double *prm, const double *lo, const d
     size_t nv = (size_t)n;
     size_t need = nv * 15 + nv * nv * 3 + nv * 10;
     double *buf = (double *)calloc(need + 8, sizeof(double));
-    int *idx = (int *)calloc(nv + 1, sizeof(int));
+    int *idx = (int *)calloc(2 * nv + 2, sizeof(int));
     ws_t w;
     memset(&w, 0, sizeof(w));
-    w.n = n; w.lo = lo; w.hi = hi; w.idx = idx;
+    w.n = n; w.lo = lo; w.hi = hi; w.idx = idx; w.lidx = idx + nv + 1;
     double *q = buf;
     w.x = q; q += nv; w.g = q; q += nv; w.gt = q; q += nv; w.xs = q; q += nv; w.s = q; q += nv;
     w.xt = q; q += nv; w.st = q; q += nv; w.r = q; q += nv; w.w = q; q += nv;
@@ -829,7 +857,7 @@ static int tron_one(int fam, int n, const double *prm, const double *lo, const d
         /* trial point and model reduction */
         for (int i = 0; i < n; i++) w.s[i] = w.xs[i] - w.x[i];
         w.fl += n;
-        double snorm = nrm2(n, w.s, &w.fl);
+        double snorm = step_norm(&w);
         gemv(n, w.H, w.s, w.hv, &w.fl);
         double gts = dot(n, w.g, w.s, &w.fl);
         double qs = gts + 0.5 * dot(n, w.s, w.hv, &w.fl);

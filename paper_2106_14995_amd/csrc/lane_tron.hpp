@@ -22,8 +22,10 @@
 //   * Steihaug CG on L^-1 A L^-T s = -L^-1 (g + Hs)_F within ||s|| <= delta, at most |F|
 //     iterations; w = L^-T s; projected search with halving (at most 20 halvings);
 //     another pass while CG ended inside the region and a free variable hit a bound.
-//   * Ratio test and radius update of TRON; when the predicted reduction is at the
-//     rounding level of f the actual reduction is taken from the gradients (trapezoid).
+//   * Ratio test and radius update of TRON; the step is measured in the norm of the trust
+//     region that bounded it (||L^T s|| on the last factored free set); when the predicted
+//     reduction is at the rounding level of f the actual reduction is taken from the
+//     gradients (trapezoid).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -292,6 +294,7 @@ struct LaneTron {
     double x[N], g[N];     // iterate and gradient
     double xs[N];          // subspace point (Cauchy point, then moved by the passes)
     double L[T], dinv[N];  // preconditioner factor and reciprocal pivots
+    uint32_t lfm;          // free set of the last factored pass (0: none this iteration)
     double f, delta, alphac;
     int32_t iters;
     int32_t cg_iters, cauchy_trials, search_trials, chol_tries;
@@ -518,6 +521,7 @@ struct LaneTron {
 
     MT_INLINE void subspace(double cg_rtol)
     {
+        lfm = 0u;
         for (int pass = 0; pass < N; pass++) {
             const uint32_t fm = free_mask(xs);
             if (fm == 0u) break;
@@ -528,6 +532,7 @@ struct LaneTron {
             hmul(s, r);
             MT_UNROLL for (int i = 0; i < N; i++) r[i] += g[i];
             precond(fm);
+            lfm = fm;
             double w[N];
             const int ex = pcg(fm, m, r, w, cg_rtol);
             bwd(w);  // w = L^-T s_hat (zero outside F)
@@ -552,6 +557,20 @@ struct LaneTron {
             const bool newly_bound = (fm & ~free_mask(xs)) != 0u;
             if (!((ex == kCgConv || ex == kCgMaxit) && newly_bound)) break;
         }
+    }
+
+    // step length in the norm of the trust region that bounded it: ||L^T s|| with the last
+    // factored pass's L (identity outside its free set), else ||s||_2
+    MT_INLINE double step_norm(const double (&s)[N]) const
+    {
+        if (lfm == 0u) return sqrt(dot(s, s));
+        double ss = 0.0;
+        MT_UNROLL for (int i = 0; i < N; i++) {
+            double t = 0.0;
+            MT_UNROLL for (int k = i; k < N; k++) t = fma(L[tri(k, i)], s[k], t);
+            ss = fma(t, t, ss);
+        }
+        return sqrt(ss);
     }
 
     MT_INLINE double radius_update(double rho, double ared, double gts, double snorm, bool fin) const
@@ -604,7 +623,7 @@ struct LaneTron {
             subspace(o.cg_rtol);
             double s[N], hs[N];
             MT_UNROLL for (int i = 0; i < N; i++) s[i] = xs[i] - x[i];
-            const double snorm = sqrt(dot(s, s));
+            const double snorm = step_norm(s);
             hmul(s, hs);
             const double gts = dot(g, s);
             const double pred = -fma(0.5, dot(s, hs), gts);

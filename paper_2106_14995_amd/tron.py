@@ -203,3 +203,52 @@ def to_device(batch, device="cuda"):
     import torch
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(device)
     return t(batch.params), t(batch.lo), t(batch.hi), t(batch.x0)
+
+
+class Admm:
+    """An admm handle over a workloads.Network (host arrays are copied at creation)."""
+
+    def __init__(self, net, branch_opts: Options | None = None, stream=None):
+        L = lib()
+        keep = [np.ascontiguousarray(a) for a in (net.br_from, net.br_to, net.br_adm, net.br_lo,
+                                                    net.br_hi, net.gen_bus, net.gen_cost,
+                                                    net.gen_lim, net.bus_load)]
+        self._net = NetworkC(net.nbus, net.nbranch, net.ngen, net.ref_bus, net.rho, net.base_mva,
+                             *[a.ctypes.data_as(C.c_void_p) for a in keep])
+        self.state_size = int(L.admm_state_size(C.byref(self._net)))
+        self._h = C.c_void_p()
+        o = branch_opts if branch_opts is not None else options()
+        _check(L.admm_create(C.byref(self._h), C.byref(self._net), C.byref(o), _stream_ptr(stream)))
+        del keep
+
+    def step(self, iters: int, resid=None, stream=None):
+        import torch
+        if resid is None:
+            resid = torch.empty(2 * max(iters, 1), dtype=torch.float64, device="cuda")
+        _check(lib().admm_step(self._h, iters, _dev(resid, torch.float64, 2 * iters, "resid"),
+                               _stream_ptr(stream)))
+        return resid[:2 * iters].view(iters, 2) if iters else resid[:0]
+
+    def get_state(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(self.state_size, dtype=torch.float64, device="cuda")
+        _check(lib().admm_get_state(self._h, _dev(out, torch.float64, self.state_size, "state"),
+                                    self.state_size, _stream_ptr(stream)))
+        return out
+
+    def set_state(self, state, stream=None):
+        import torch
+        _check(lib().admm_set_state(self._h, _dev(state, torch.float64, self.state_size, "state"),
+                                    self.state_size, _stream_ptr(stream)))
+
+    def close(self):
+        if self._h:
+            lib().admm_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
