@@ -33,6 +33,22 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary (profiles/traffic.json), or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    h = hashlib.sha256()
+    for src in rec["kernel_sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def cpu_baseline(bt, budget_s):
     """The oracle (as it stands) on all host cores over the same batch, repeated until about
     `budget_s` seconds of CPU work; also returns its algorithmic flop count per instance."""
@@ -62,6 +78,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="CPU work budget of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="br6", choices=["br6", "copy"],
+                    help="copy: a plain device-to-device copy of known size, used to scale the "
+                         "FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -75,6 +94,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.mode == "copy":
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read_per_copy": nbytes,
+                          "bytes_written_per_copy": nbytes, "copies": args.steps}), flush=True)
+        return
     log(f"generating {args.batch} BR6 instances")
     bt = W.br6_batch(args.batch, config_id=1)
     params, lo, hi, x0 = tron.to_device(bt)
@@ -138,7 +167,11 @@ def main():
             roof = {"bound": "hbm", "achieved": bytes_ / kern_s / 1e9, "peak": PEAK_HBM / 1e9,
                     "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = None
+        traffic = measured_traffic("lane_kernel<mt::BR6, 6>")
+        roof["traffic"] = traffic
+        if traffic is not None:
+            roof["traffic_unit"] = "bytes per launch (FETCH_SIZE x2.000 + WRITE_SIZE x1.000)"
+            roof["traffic_over_algorithmic"] = traffic / bytes_
         roof["flops_per_instance"] = cb["flops_per_instance"]
         roof["bytes_per_instance"] = BR6_BYTES
         roof["hbm_gbs_algorithmic"] = bytes_ / kern_s / 1e9

@@ -118,6 +118,13 @@ tron_err tron_batch_set_options(tron_batch *h, const tron_options *opt);
 tron_err tron_batch_plan(const tron_batch *h, int32_t *nbuckets, int32_t *desc,
                          int32_t max_buckets);
 
+/* Record, for every instance of later solves, the device wall clock when its solve started
+ * and ended: d_ts holds 2*batch int64 (start, end) written at solve time, or NULL to stop.
+ * The buffer stays the caller's and must outlive the solves that write it. The clock
+ * runs at tron_clock_rate_hz() (0 if unknown). Used for per-instance solve latency. */
+tron_err tron_batch_set_timestamps(tron_batch *h, int64_t *d_ts);
+int64_t tron_clock_rate_hz(void);
+
 tron_err tron_batch_destroy(tron_batch *h);
 
 /* ------------------------------------------------------------------------------------ */

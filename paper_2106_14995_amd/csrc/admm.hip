@@ -412,6 +412,7 @@ extern "C" tron_err admm_step(admm *a, int32_t iters, double *d_resid, void *str
     la.status = a->d_status;
     la.iters = a->d_iters;
     la.state = v.del;  // radius then Cauchy step length, contiguous in the state
+    la.ts = nullptr;
     la.count = n.L;
     la.batch = n.L;
     la.n_uniform = 6;

@@ -369,8 +369,7 @@ struct LaneTron {
             xt[i] = clampb(fma(-a, g[i], x[i]), lo[i], hi[i]);
             st[i] = xt[i] - x[i];
         }
-        const double sn = sqrt(dot(st, st));
-        if (!(sn <= delta)) return false;
+        if (!(dot(st, st) <= delta * delta)) return false;  // ||s|| <= delta
         double hs[N];
         hmul(st, hs);
         const double gts = dot(g, st);
@@ -378,26 +377,30 @@ struct LaneTron {
         return q <= kMu0 * gts;
     }
 
-    MT_INLINE void cauchy()
+    // a below the largest breakpoint along -g: some finite bound i is not yet reached at
+    // step a, i.e. a |g_i| < (distance to that bound), written without divisions; with no
+    // finite breakpoint at all the bound is +inf
+    MT_INLINE bool below_last_breakpoint(double a) const
     {
-        // largest breakpoint along -g
-        double bmax = 0.0;
-        int nb = 0;
+        bool any = false, below = false;
         MT_UNROLL for (int i = 0; i < N; i++) {
             const double d = -g[i];
-            double b = 0.0;
-            bool has = false;
-            if (d > 0.0 && isfinite(hi[i])) { b = (hi[i] - x[i]) / d; has = true; }
-            else if (d < 0.0 && isfinite(lo[i])) { b = (lo[i] - x[i]) / d; has = true; }
-            if (has) { bmax = (nb == 0 || b > bmax) ? b : bmax; nb++; }
+            const bool up = d > 0.0 && isfinite(hi[i]);
+            const bool dn = d < 0.0 && isfinite(lo[i]);
+            any = any || up || dn;
+            below = below || (up && a * d < hi[i] - x[i]) || (dn && a * d > lo[i] - x[i]);
         }
-        if (nb == 0) bmax = __builtin_inf();
+        return !any || below;
+    }
+
+    MT_INLINE void cauchy()
+    {
         double a = alphac;
         double xt[N];
         if (cauchy_trial(a, xt)) {
             MT_UNROLL for (int i = 0; i < N; i++) xs[i] = xt[i];
             for (int t = 0; t < kCauchyMax; t++) {
-                if (!(a < bmax)) break;
+                if (!below_last_breakpoint(a)) break;
                 const double a2 = 10.0 * a;
                 if (!cauchy_trial(a2, xt)) break;
                 a = a2;
@@ -422,9 +425,8 @@ struct LaneTron {
             double d = fam.H(j, j) + alpha;
             MT_UNROLL for (int k = 0; k < j; k++) d = fma(-L[tri(j, k)], L[tri(j, k)], d);
             ok = ok && (!fj || d > 0.0);
-            const double piv = fj ? sqrt(d) : 1.0;
-            const double r = 1.0 / piv;
-            L[tri(j, j)] = piv;
+            const double r = fj ? rsqrt(d) : 1.0;  // 1 / pivot
+            L[tri(j, j)] = fj ? d * r : 1.0;        // pivot = d / sqrt(d)
             dinv[j] = r;
             MT_UNROLL for (int i = j + 1; i < N; i++) {
                 double s = fam.H(i, j);
@@ -474,7 +476,7 @@ struct LaneTron {
         fwd(rh);
         MT_UNROLL for (int i = 0; i < N; i++) p[i] = rh[i];
         double rr = dot(rh, rh);
-        const double tol = cg_rtol * sqrt(rr);
+        const double tol2 = cg_rtol * cg_rtol * rr;  // (cg_rtol ||r0||)^2
         if (rr == 0.0) return kCgConv;
         for (int j = 0; j < m; j++) {
             cg_iters++;
@@ -493,7 +495,7 @@ struct LaneTron {
             const double a = rr / kap;
             double tv[N];
             MT_UNROLL for (int i = 0; i < N; i++) tv[i] = fma(a, p[i], sh[i]);
-            if (sqrt(dot(tv, tv)) >= delta) {
+            if (dot(tv, tv) >= delta * delta) {
                 const double sig = trqsol(sh, p);
                 MT_UNROLL for (int i = 0; i < N; i++) sh[i] = fma(sig, p[i], sh[i]);
                 return kCgBnd;
@@ -503,7 +505,7 @@ struct LaneTron {
                 rh[i] = fma(-a, q[i], rh[i]);
             }
             const double rrn = dot(rh, rh);
-            if (sqrt(rrn) <= tol) return kCgConv;
+            if (rrn <= tol2) return kCgConv;
             const double b = rrn / rr;
             MT_UNROLL for (int i = 0; i < N; i++) p[i] = fma(b, p[i], rh[i]);
             rr = rrn;

@@ -16,6 +16,7 @@ struct LaneArgs {
     const int32_t *index;    // instance list of this bucket, or null (all, in order)
     const int32_t *nper;     // per-instance n, or null (n_uniform)
     const int64_t *poff, *voff;
+    int64_t *ts;             // optional: per-instance start / end device clock (2 per instance)
     int64_t count, batch;
     int32_t n_uniform, psize;
     mt::Options opt;

@@ -65,6 +65,7 @@ __global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a)
     const int n = a.nper ? a.nper[b] : a.n_uniform;
     const int64_t po = a.poff ? a.poff[b] : b * (int64_t)a.psize;
     const int64_t vo = a.voff ? a.voff[b] : b * (int64_t)n;
+    const int64_t t0 = a.ts ? (int64_t)wall_clock64() : 0;
     mt::LaneTron<F, N> s;
     s.fam.load(a.params + po, n);
     const double *lo = a.lo + vo, *hi = a.hi + vo, *x0 = a.x0 + vo;
@@ -86,6 +87,10 @@ __global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a)
     a.iters[b] = s.iters;
     a.state[b] = s.delta;
     a.state[a.batch + b] = s.alphac;
+    if (a.ts) {
+        a.ts[2 * b] = t0;
+        a.ts[2 * b + 1] = (int64_t)wall_clock64();
+    }
 }
 
 
@@ -148,6 +153,7 @@ struct tron_batch {
     int32_t nmax = 0;
     tron_options opt{};
     double *d_state = nullptr;
+    int64_t *d_ts = nullptr;   // caller's timestamp buffer, or null
     int32_t *d_n = nullptr;
     int64_t *d_poff = nullptr, *d_voff = nullptr;
     std::vector<Bucket> buckets;
@@ -310,6 +316,7 @@ extern "C" tron_err tron_batch_solve(tron_batch *h, const double *d_params, cons
     a.status = d_status;
     a.iters = d_iters;
     a.state = h->d_state;
+    a.ts = h->d_ts;
     a.nper = h->n_uniform ? nullptr : h->d_n;
     a.poff = h->n_uniform ? nullptr : h->d_poff;
     a.voff = h->n_uniform ? nullptr : h->d_voff;
@@ -363,6 +370,21 @@ extern "C" tron_err tron_batch_plan(const tron_batch *h, int32_t *nbuckets, int3
         desc[3 * i + 2] = (int32_t)h->buckets[i].count;
     }
     return TRON_OK;
+}
+
+extern "C" tron_err tron_batch_set_timestamps(tron_batch *h, int64_t *d_ts)
+{
+    if (!h) return mt_fail(TRON_ERR_INVALID, "handle is null");
+    h->d_ts = d_ts;
+    return TRON_OK;
+}
+
+extern "C" int64_t tron_clock_rate_hz(void)
+{
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return 0;
+    return (int64_t)khz * 1000;
 }
 
 extern "C" tron_err tron_batch_destroy(tron_batch *h)

@@ -4,6 +4,15 @@ Tolerances (per instance, f and the projected gradient re-evaluated by the oracl
 evaluator at the GPU's x):
   strictly convex (QP4):  |f_gpu - f_oracle| <= 1e-8 max(1, |f_oracle|), ||x_gpu - x_oracle||_inf <= 1e-6
   nonconvex (BR6, HS45M): ||grad_[l,u] f(x_gpu)||_inf <= 1e-6 and f(x_gpu) <= f_oracle + 1e-8
+
+Trajectory splits: the GPU and the oracle run the same steps with different rounding (FMA
+contraction, reciprocal pivots). A discrete decision taken on a rounded value (the stop
+test pg <= gtol, a Cauchy or line-search acceptance) can go differently when the value lands
+within rounding of its threshold; both runs then still converge, but with a
+strong-convexity modulus near 0.1 their x can differ by up to ~gtol/0.1. For strictly
+convex problems the minimiser x* is unique, so such an instance passes when the GPU's x is
+at least as close to x* (the oracle run to gtol = 1e-13) as the oracle's own x; these
+splits must stay below 1 % of the instances and are reported.
 """
 import numpy as np
 import pytest
@@ -53,8 +62,15 @@ def check_parity(bt, g, ref, convex, idx=None):
         pg = oracle.projgrad_inf(xg, lo, hi, oracle.eval_g(bt.family, n, p, xg))
         worst["pg"] = max(worst["pg"], pg)
         if convex:
+            assert pg <= PG_TOL, (b, pg)
             df = abs(fg - fo_ref) / max(1.0, abs(fo_ref))
             dx = np.abs(xg - xo).max() if n else 0.0
+            if dx > CONVEX_X:
+                # trajectory split: compare distances to the unique minimiser
+                xs = oracle.solve(bt.subset([b]), gtol=1e-13, nthreads=1)["x"]
+                if np.abs(xg - xs).max() <= np.abs(xo - xs).max() + 1e-9:
+                    worst["splits"] = worst.get("splits", 0) + 1
+                    dx = 0.0
             worst["df"] = max(worst["df"], df)
             worst["dx"] = max(worst["dx"], dx)
             assert df <= CONVEX_F, (b, fg, fo_ref)
@@ -62,6 +78,7 @@ def check_parity(bt, g, ref, convex, idx=None):
         else:
             assert pg <= PG_TOL, (b, pg)
             assert fg <= fo_ref + NONCONVEX_F, (b, fg, fo_ref)
+    assert worst.get("splits", 0) <= max(2, len(idx) // 100), worst
     return worst
 
 
@@ -77,6 +94,7 @@ def test_qp4_config0(tron):
     g = gpu_solve(tron, bt)
     ref = oracle_ref(bt)
     w = check_parity(bt, g, ref, convex=True)
+    print("worst", w)
     assert w["pg"] <= PG_TOL
     # same algorithm: iteration counts agree on (almost) every instance
     assert np.mean(g["iters"] == ref["iters"]) >= 0.95
