@@ -13,6 +13,7 @@
 #include "lane_tron.hpp"
 #include "tron.h"
 #include "tron_internal.hpp"
+#include "wave_tron.hpp"
 
 // ------------------------------------------------------------------------------------
 // error reporting
@@ -135,15 +136,81 @@ static lane_launch_fn lane_launcher(tron_family fam, int N)
 void mt_launch_br6(const LaneArgs &a, hipStream_t st) { launch_lane<mt::BR6, 6>(a, st); }
 
 // ------------------------------------------------------------------------------------
+// wavefront-per-instance kernels (8 < n <= 128, QP4); one 64-lane workgroup per instance,
+// so the hardware dispatcher hands the next instance to whichever CU frees up first
+// ------------------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(64) void wave_kernel(LaneArgs a)
+{
+    extern __shared__ double smem[];
+    const int64_t t = blockIdx.x;
+    if (t >= a.count) return;
+    const int64_t b = a.index ? (int64_t)a.index[t] : t;
+    const int n = a.nper ? a.nper[b] : a.n_uniform;
+    const int64_t po = a.poff ? a.poff[b] : b * (int64_t)a.psize;
+    const int64_t vo = a.voff ? a.voff[b] : b * (int64_t)n;
+    const int64_t t0 = a.ts ? (int64_t)wall_clock64() : 0;
+    mt::WaveQP4<R> s;
+    s.n = n;
+    s.ld = n | 1;
+    s.lane = threadIdx.x;
+    s.M = smem;
+    s.load(a.params + po, a.lo + vo, a.hi + vo, a.x0 + vo);
+    const double din = a.opt.warm ? a.state[b] : 0.0;
+    const double ain = a.opt.warm ? a.state[a.batch + b] : 0.0;
+    const int32_t st = s.solve(a.opt, din, ain);
+    double *xo = a.x + vo;
+    MT_UNROLL for (int r = 0; r < R; r++)
+        if (s.valid(r)) xo[s.row(r)] = s.x[r];
+    if (threadIdx.x == 0) {
+        a.f[b] = s.f;
+        a.status[b] = st;
+        a.iters[b] = s.iters;
+        a.state[b] = s.delta;
+        a.state[a.batch + b] = s.alphac;
+        if (a.ts) {
+            a.ts[2 * b] = t0;
+            a.ts[2 * b + 1] = (int64_t)wall_clock64();
+        }
+    }
+}
+
+static size_t wave_lds_bytes(int nmax) { return sizeof(double) * (size_t)nmax * (size_t)(nmax | 1); }
+
+template <int R>
+static void launch_wave(const LaneArgs &a, int nmax, hipStream_t st)
+{
+    if (a.count <= 0) return;
+    const size_t lds = wave_lds_bytes(nmax);
+    static bool attr_set = false;
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)wave_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)wave_lds_bytes(64 * R));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((wave_kernel<R>), dim3((unsigned)a.count), dim3(64), lds, st, a);
+}
+
+// ------------------------------------------------------------------------------------
 // batch handle
 // ------------------------------------------------------------------------------------
 struct Bucket {
-    int32_t nmax;      // compile-time size of the kernel
-    int32_t lanes;     // lanes per instance
+    int32_t nmax;      // largest n the bucket's kernel holds
+    int32_t lanes;     // lanes per instance (1: lane kernel, 64: wave kernel)
     int64_t count;     // instances in the bucket
     int32_t *d_index;  // instance list (null when the bucket is the whole batch in order)
     lane_launch_fn lane;
 };
+
+static void launch_bucket(const Bucket &b, const LaneArgs &a, hipStream_t st)
+{
+    if (b.lanes == 1) b.lane(a, st);
+    else if (b.nmax <= 64) launch_wave<1>(a, b.nmax, st);
+    else launch_wave<2>(a, b.nmax, st);
+}
+
+// bucket of the wave kernel for n > 8: the next of 16, 32, 64, 128
+static int wave_nmax(int n) { return n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 128; }
 
 struct tron_batch {
     int device = 0;
@@ -190,38 +257,67 @@ static tron_err check_options(const tron_options &o)
 
 // Buckets of the lane kernel: instances grouped by the smallest supported kernel size
 // that holds them (sizes 1..8 each get their own kernel).
+// Launch plan: n <= 8 goes to the lane kernel of exactly that n (one instance per lane);
+// larger n to the wave kernel of the next size in 16, 32, 64, 128 (one instance per
+// wavefront, LDS sized for the bucket), with the bucket's instances ordered largest first
+// so the longest solves start earliest. Heaviest buckets are launched first.
 static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStream_t st)
 {
     if (h->batch == 0) return TRON_OK;
     if (h->n_uniform) {
         Bucket b{};
-        b.nmax = h->n_uniform;
-        b.lanes = 1;
         b.count = h->batch;
         b.d_index = nullptr;
-        b.lane = lane_launcher(h->fam, h->n_uniform);
-        if (!b.lane) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d not supported for this family", h->n_uniform);
+        if (h->n_uniform <= 8) {
+            b.nmax = h->n_uniform;
+            b.lanes = 1;
+            b.lane = lane_launcher(h->fam, h->n_uniform);
+            if (!b.lane) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d not supported for this family", h->n_uniform);
+        } else {
+            if (h->fam != TRON_FAMILY_QP4) return mt_fail(TRON_ERR_UNSUPPORTED, "n > 8 needs QP4");
+            b.nmax = h->n_uniform;
+            b.lanes = 64;
+            b.lane = nullptr;
+        }
         h->buckets.push_back(b);
         return TRON_OK;
     }
-    std::vector<std::vector<int32_t>> lists(9);
+    std::vector<std::vector<int32_t>> lane_lists(9);
+    std::vector<std::vector<int32_t>> wave_lists(4);  // 16, 32, 64, 128
     for (int64_t i = 0; i < h->batch; i++) {
-        if (n[i] > 8) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d exceeds the lane kernel", n[i]);
-        lists[n[i]].push_back((int32_t)i);
+        if (n[i] <= 8) lane_lists[n[i]].push_back((int32_t)i);
+        else {
+            if (h->fam != TRON_FAMILY_QP4) return mt_fail(TRON_ERR_UNSUPPORTED, "n > 8 needs QP4");
+            const int w = wave_nmax(n[i]);
+            wave_lists[w == 16 ? 0 : w == 32 ? 1 : w == 64 ? 2 : 3].push_back((int32_t)i);
+        }
     }
-    for (int k = 1; k <= 8; k++) {
-        if (lists[k].empty()) continue;
+    auto add = [&](std::vector<int32_t> &list, int nmax, int lanes) -> tron_err {
         Bucket b{};
-        b.nmax = k;
-        b.lanes = 1;
-        b.count = (int64_t)lists[k].size();
-        b.lane = lane_launcher(h->fam, k);
-        if (!b.lane) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d not supported for this family", k);
-        HIP_TRY(hipMalloc(&b.d_index, sizeof(int32_t) * lists[k].size()));
-        HIP_TRY(hipMemcpyAsync(b.d_index, lists[k].data(), sizeof(int32_t) * lists[k].size(),
-                               hipMemcpyHostToDevice, st));
+        b.nmax = nmax;
+        b.lanes = lanes;
+        b.count = (int64_t)list.size();
+        b.lane = lanes == 1 ? lane_launcher(h->fam, nmax) : nullptr;
+        if (lanes == 1 && !b.lane) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d not supported for this family", nmax);
+        HIP_TRY(hipMalloc(&b.d_index, sizeof(int32_t) * list.size()));
+        HIP_TRY(hipMemcpyAsync(b.d_index, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, st));
         h->buckets.push_back(b);
+        return TRON_OK;
+    };
+    for (int w = 3; w >= 0; w--) {
+        auto &list = wave_lists[w];
+        if (list.empty()) continue;
+        std::stable_sort(list.begin(), list.end(), [&](int32_t a, int32_t b) { return n[a] > n[b]; });
+        tron_err rc = add(list, 16 << w, 64);
+        if (rc != TRON_OK) return rc;
     }
+    for (int k = 8; k >= 1; k--) {
+        if (lane_lists[k].empty()) continue;
+        tron_err rc = add(lane_lists[k], k, 1);
+        if (rc != TRON_OK) return rc;
+    }
+    // the device copies above read host vectors that die with this call
+    HIP_TRY(hipStreamSynchronize(st));
     return TRON_OK;
 }
 
@@ -327,7 +423,7 @@ extern "C" tron_err tron_batch_solve(tron_batch *h, const double *d_params, cons
     for (const Bucket &b : h->buckets) {
         a.index = b.d_index;
         a.count = b.count;
-        b.lane(a, st);
+        launch_bucket(b, a, st);
     }
     HIP_TRY(hipGetLastError());
     return TRON_OK;

@@ -1,0 +1,543 @@
+// wave_tron.hpp -- one trust-region Newton solve per wavefront, for 8 < n <= 128.
+//
+// Lane l of the wave owns rows i = l and i = l + 64 (R = 2 only for n > 64) of every
+// vector. The n x n Hessian and its Cholesky factor share one LDS array of row stride ld
+// (odd, so that both row and column walks touch distinct banks): the factor L in the lower
+// triangle with its diagonal, the Hessian's strict upper triangle above it; the Hessian's
+// diagonal stays in registers. Every decision of the method is taken on wave-reduced,
+// wave-uniform values (the free set is a 64-bit ballot), so the 64 lanes never diverge.
+// Sums use a butterfly of lane swaps (every lane ends with the same bits); the pivots and
+// solution components of the triangular solves are broadcast with readlane.
+//
+// The steps and readings are those of lane_tron.hpp (Algorithm 1 with the TRON ratio test,
+// the step measured in the trust region's norm, and the trapezoid reduction near rounding
+// level); only the data layout differs.
+#pragma once
+
+#include "lane_tron.hpp"
+
+namespace mt {
+
+MT_INLINE double wave_sum(double v)
+{
+    MT_UNROLL for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// make a value the compiler treats as per-lane into a scalar (all lanes hold the same bits)
+MT_INLINE double uni(double v)
+{
+    const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+    const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+MT_INLINE double bcast(double v, int src)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+MT_INLINE double wave_max(double v)
+{
+    MT_UNROLL for (int m = 32; m >= 1; m >>= 1) {
+        const double o = __shfl_xor(v, m);
+        v = (o > v || o != o) ? o : v;  // NaN propagates
+    }
+    return v;
+}
+
+// QP4 solved by one wave, R rows per lane (n <= 64 R).
+template <int R>
+struct WaveQP4 {
+    int n, ld, lane;
+    double *M;                 // LDS: L lower with diagonal, H strict upper, row stride ld
+    double qd[R], c[R], hd[R]; // Q diagonal, c, H diagonal (own rows)
+    double kap;
+    double lo[R], hi[R], x[R], g[R], xs[R], dinv[R];
+    uint64_t lfm[R];           // free set of the last factored pass
+    bool has_l;
+    double f, delta, alphac;
+    int32_t iters;
+
+    MT_INLINE int row(int r) const { return lane + 64 * r; }
+    MT_INLINE bool valid(int r) const { return row(r) < n; }
+
+    MT_INLINE double dot(const double (&a)[R], const double (&b)[R]) const
+    {
+        double s = 0.0;
+        MT_UNROLL for (int r = 0; r < R; r++) s = fma(a[r], b[r], s);
+        return uni(wave_sum(s));
+    }
+
+    // y = A v over the first n rows, A = H with diagonal diag (Q's or H's); rows >= n give 0
+    MT_INLINE void amul(const double (&v)[R], const double (&diag)[R], double (&y)[R]) const
+    {
+        MT_UNROLL for (int r = 0; r < R; r++) y[r] = 0.0;
+        MT_UNROLL for (int rr = 0; rr < R; rr++) {
+            const int jend = n - 64 * rr < 64 ? n - 64 * rr : 64;
+            for (int jj = 0; jj < jend; jj++) {
+                const int j = 64 * rr + jj;
+                const double vj = bcast(v[rr], jj);
+                MT_UNROLL for (int r = 0; r < R; r++) {
+                    const int i = row(r);
+                    const int k = i < n ? i : 0;
+                    const double h0 = M[j < k ? j * ld + k : k * ld + j];  // H_kj from the upper triangle
+                    const double h = j == k ? diag[r] : h0;
+                    y[r] = fma(h, vj, y[r]);
+                }
+            }
+        }
+        MT_UNROLL for (int r = 0; r < R; r++) y[r] = valid(r) ? y[r] : 0.0;
+    }
+
+    MT_INLINE void load(const double *__restrict__ p, const double *__restrict__ lop,
+                        const double *__restrict__ hip_, const double *__restrict__ x0p)
+    {
+        const double *cp = p + n * (n + 1) / 2;
+        kap = cp[n];
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const int i = row(r);
+            const bool in = i < n;
+            const int k = in ? i : 0;
+            qd[r] = in ? p[k * (k + 1) / 2 + k] : 0.0;
+            c[r] = in ? cp[k] : 0.0;
+            lo[r] = in ? lop[k] : 0.0;
+            hi[r] = in ? hip_[k] : 0.0;
+            x[r] = in ? x0p[k] : 0.0;
+        }
+        // strict upper part of Q (row i, column j > i = packed lower entry (j, i)); at each j
+        // the lanes i < j read consecutive addresses
+        for (int j = 1; j < n; j++) {
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = row(r);
+                if (i < j) M[i * ld + j] = p[j * (j + 1) / 2 + i];
+            }
+        }
+    }
+
+    MT_INLINE double fg(const double (&v)[R], double (&gr)[R]) const
+    {
+        double y[R];
+        amul(v, qd, y);
+        double s = 0.0;
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const double x2 = v[r] * v[r];
+            gr[r] = valid(r) ? fma(4.0 * kap * x2, v[r], y[r] + c[r]) : 0.0;
+            s = fma(v[r], fma(0.5, y[r], c[r]), s);
+            s = fma(kap * x2, x2, s);
+        }
+        return uni(wave_sum(s));
+    }
+
+    MT_INLINE void hess()
+    {
+        MT_UNROLL for (int r = 0; r < R; r++) hd[r] = fma(12.0 * kap * x[r], x[r], qd[r]);
+    }
+
+    MT_INLINE double pg_inf() const
+    {
+        double m = 0.0;
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const double v = valid(r) ? fabs(pg_comp(x[r], lo[r], hi[r], g[r])) : 0.0;
+            m = (!(v <= m)) ? v : m;
+        }
+        return uni(wave_max(m));
+    }
+
+    MT_INLINE double pg_nrm2() const
+    {
+        double s = 0.0;
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const double v = valid(r) ? pg_comp(x[r], lo[r], hi[r], g[r]) : 0.0;
+            s = fma(v, v, s);
+        }
+        return sqrt(uni(wave_sum(s)));
+    }
+
+    MT_INLINE bool is_free(const uint64_t (&fm)[R], int j) const { return (fm[j >> 6] >> (j & 63)) & 1ull; }
+    MT_INLINE bool own_free(const uint64_t (&fm)[R], int r) const { return (fm[r] >> lane) & 1ull; }
+
+    // masked left-looking Cholesky of H_FF + alpha I (identity outside F)
+    MT_INLINE bool chol(const uint64_t (&fm)[R], double alpha)
+    {
+        for (int j = 0; j < n; j++) {
+            const int rj = j >> 6, lj = j & 63;
+            const bool fj = is_free(fm, j);
+            double s[R];
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = row(r);
+                const int k = i < n ? i : 0;
+                double a;
+                if (k > j) a = M[j * ld + k];            // H_ij from the upper triangle
+                else a = hd[r] + alpha;                   // only used when i == j
+                if (fj && k >= j) {
+                    for (int q = 0; q < j; q++) a = fma(-M[k * ld + q], M[j * ld + q], a);
+                }
+                s[r] = a;
+            }
+            const double d = uni(bcast(s[rj], lj));
+            if (fj && !(d > 0.0)) return false;
+            const double rinv = fj ? rsqrt(d) : 1.0;
+            const double piv = fj ? d * rinv : 1.0;
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = row(r);
+                if (i < n && i > j) M[i * ld + j] = (fj && own_free(fm, r)) ? s[r] * rinv : 0.0;
+                if (i == j) {
+                    M[i * ld + i] = piv;
+                    dinv[r] = rinv;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        return true;
+    }
+
+    MT_INLINE void precond(const uint64_t (&fm)[R])
+    {
+        double mn = __builtin_inf(), mx = 0.0;
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            if (valid(r) && own_free(fm, r)) {
+                mn = hd[r] < mn ? hd[r] : mn;
+                mx = fabs(hd[r]) > mx ? fabs(hd[r]) : mx;
+            }
+        }
+        mn = -uni(wave_max(-mn));
+        mx = uni(wave_max(mx));
+        const double beta = 1e-3 * (mx > 1.0 ? mx : 1.0);
+        double alpha = mn > 0.0 ? 0.0 : beta - mn;
+        for (int t = 0; t < kShiftTries; t++) {
+            if (chol(fm, alpha)) return;
+            alpha = 2.0 * alpha > beta ? 2.0 * alpha : beta;
+        }
+        for (int j = 0; j < n; j++) {
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = row(r);
+                if (i < n && i > j) M[i * ld + j] = 0.0;
+            }
+        }
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const int i = row(r);
+            if (i < n) {
+                const double v = fabs(hd[r]);
+                const double piv = own_free(fm, r) ? sqrt(v > beta ? v : beta) : 1.0;
+                M[i * ld + i] = piv;
+                dinv[r] = 1.0 / piv;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
+    // L y = b in place (b zero outside the factored set stays zero)
+    MT_INLINE void fwd(double (&b)[R]) const
+    {
+        for (int j = 0; j < n; j++) {
+            const int rj = j >> 6, lj = j & 63;
+            double yj = 0.0;
+            MT_UNROLL for (int r = 0; r < R; r++)
+                if (r == rj) yj = b[r] * dinv[r];
+            yj = uni(bcast(yj, lj));
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = row(r);
+                if (i == j) b[r] = yj;
+                else if (i > j && i < n) b[r] = fma(-M[i * ld + j], yj, b[r]);
+            }
+        }
+    }
+
+    // L^T y = b in place
+    MT_INLINE void bwd(double (&b)[R]) const
+    {
+        for (int j = n - 1; j >= 0; j--) {
+            const int rj = j >> 6, lj = j & 63;
+            double yj = 0.0;
+            MT_UNROLL for (int r = 0; r < R; r++)
+                if (r == rj) yj = b[r] * dinv[r];
+            yj = uni(bcast(yj, lj));
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = row(r);
+                if (i == j) b[r] = yj;
+                else if (i < j) b[r] = fma(-M[j * ld + i], yj, b[r]);
+            }
+        }
+    }
+
+    MT_INLINE double trqsol(const double (&v)[R], const double (&p)[R]) const
+    {
+        const double ptx = dot(p, v), ptp = dot(p, p), xtx = dot(v, v);
+        const double dsq = delta * delta;
+        double disc = fma(ptx, ptx, ptp * (dsq - xtx));
+        disc = disc < 0.0 ? 0.0 : disc;
+        const double rad = sqrt(disc);
+        const double sig = ptx >= 0.0 ? (dsq - xtx) / (ptx + rad) : (rad - ptx) / ptp;
+        return sig > 0.0 ? sig : 0.0;
+    }
+
+    MT_INLINE bool cauchy_trial(double a, double (&xt)[R])
+    {
+        double st[R], hs[R];
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            xt[r] = clampb(fma(-a, g[r], x[r]), lo[r], hi[r]);
+            st[r] = xt[r] - x[r];
+        }
+        if (!(dot(st, st) <= delta * delta)) return false;
+        amul(st, hd, hs);
+        double ss[R];
+        MT_UNROLL for (int r = 0; r < R; r++) ss[r] = fma(0.5, hs[r], g[r]);
+        const double gts = dot(g, st);
+        const double q = dot(st, ss);  // g's + s'Hs/2
+        return q <= kMu0 * gts;
+    }
+
+    MT_INLINE bool below_last_breakpoint(double a) const
+    {
+        bool any = false, below = false;
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const double d = -g[r];
+            const bool up = valid(r) && d > 0.0 && isfinite(hi[r]);
+            const bool dn = valid(r) && d < 0.0 && isfinite(lo[r]);
+            any = any || up || dn;
+            below = below || (up && a * d < hi[r] - x[r]) || (dn && a * d > lo[r] - x[r]);
+        }
+        const bool wany = __ballot(any) != 0ull, wbelow = __ballot(below) != 0ull;
+        return !wany || wbelow;
+    }
+
+    MT_INLINE void cauchy()
+    {
+        double a = alphac;
+        double xt[R];
+        if (cauchy_trial(a, xt)) {
+            MT_UNROLL for (int r = 0; r < R; r++) xs[r] = xt[r];
+            for (int t = 0; t < kCauchyMax; t++) {
+                if (!below_last_breakpoint(a)) break;
+                const double a2 = 10.0 * a;
+                if (!cauchy_trial(a2, xt)) break;
+                a = a2;
+                MT_UNROLL for (int r = 0; r < R; r++) xs[r] = xt[r];
+            }
+        } else {
+            for (int t = 0; t < kCauchyMax; t++) {
+                a = 0.1 * a;
+                if (cauchy_trial(a, xt)) break;
+            }
+            MT_UNROLL for (int r = 0; r < R; r++) xs[r] = xt[r];
+        }
+        alphac = a;
+    }
+
+    MT_INLINE void free_mask(const double (&v)[R], uint64_t (&fm)[R]) const
+    {
+        MT_UNROLL for (int r = 0; r < R; r++) fm[r] = __ballot(valid(r) && lo[r] < v[r] && v[r] < hi[r]);
+    }
+
+    MT_INLINE int pcg(const uint64_t (&fm)[R], int m, const double (&rv)[R], double (&sh)[R],
+                      double cg_rtol)
+    {
+        double rh[R], p[R];
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            rh[r] = own_free(fm, r) ? -rv[r] : 0.0;
+            sh[r] = 0.0;
+        }
+        fwd(rh);
+        MT_UNROLL for (int r = 0; r < R; r++) p[r] = rh[r];
+        double rr = dot(rh, rh);
+        const double tol2 = cg_rtol * cg_rtol * rr;
+        if (rr == 0.0) return kCgConv;
+        for (int j = 0; j < m; j++) {
+            double z[R], q[R];
+            MT_UNROLL for (int r = 0; r < R; r++) z[r] = p[r];
+            bwd(z);
+            amul(z, hd, q);
+            MT_UNROLL for (int r = 0; r < R; r++) q[r] = own_free(fm, r) ? q[r] : 0.0;
+            fwd(q);
+            const double kap_ = dot(p, q);
+            if (!(kap_ > 0.0)) {
+                const double sig = trqsol(sh, p);
+                MT_UNROLL for (int r = 0; r < R; r++) sh[r] = fma(sig, p[r], sh[r]);
+                return kCgNeg;
+            }
+            const double a = rr / kap_;
+            double tv[R];
+            MT_UNROLL for (int r = 0; r < R; r++) tv[r] = fma(a, p[r], sh[r]);
+            if (dot(tv, tv) >= delta * delta) {
+                const double sig = trqsol(sh, p);
+                MT_UNROLL for (int r = 0; r < R; r++) sh[r] = fma(sig, p[r], sh[r]);
+                return kCgBnd;
+            }
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                sh[r] = tv[r];
+                rh[r] = fma(-a, q[r], rh[r]);
+            }
+            const double rrn = dot(rh, rh);
+            if (rrn <= tol2) return kCgConv;
+            const double b = rrn / rr;
+            MT_UNROLL for (int r = 0; r < R; r++) p[r] = fma(b, p[r], rh[r]);
+            rr = rrn;
+        }
+        return kCgMaxit;
+    }
+
+    MT_INLINE void subspace(double cg_rtol)
+    {
+        has_l = false;
+        for (int pass = 0; pass < n; pass++) {
+            uint64_t fm[R];
+            free_mask(xs, fm);
+            int m = 0;
+            MT_UNROLL for (int r = 0; r < R; r++) m += __builtin_popcountll(fm[r]);
+            if (m == 0) break;
+            double s[R], rv[R];
+            MT_UNROLL for (int r = 0; r < R; r++) s[r] = xs[r] - x[r];
+            amul(s, hd, rv);
+            MT_UNROLL for (int r = 0; r < R; r++) rv[r] += g[r];
+            precond(fm);
+            has_l = true;
+            MT_UNROLL for (int r = 0; r < R; r++) lfm[r] = fm[r];
+            double w[R];
+            const int ex = pcg(fm, m, rv, w, cg_rtol);
+            bwd(w);
+            double beta = 1.0;
+            bool acc = false;
+            double xt[R];
+            for (int t = 0; t <= kSearchHalvings; t++) {
+                double d[R], hdv[R];
+                MT_UNROLL for (int r = 0; r < R; r++) {
+                    xt[r] = clampb(fma(beta, w[r], xs[r]), lo[r], hi[r]);
+                    d[r] = xt[r] - xs[r];
+                }
+                amul(d, hd, hdv);
+                double hh[R];
+                MT_UNROLL for (int r = 0; r < R; r++) hh[r] = fma(0.5, hdv[r], rv[r]);
+                const double rd = dot(rv, d);
+                const double dq = dot(d, hh);  // r'd + d'Hd/2
+                if (dq <= kMu0 * rd) { acc = true; break; }
+                beta *= 0.5;
+            }
+            if (acc) MT_UNROLL for (int r = 0; r < R; r++) xs[r] = xt[r];
+            uint64_t fm2[R];
+            free_mask(xs, fm2);
+            bool newly = false;
+            MT_UNROLL for (int r = 0; r < R; r++) newly = newly || (fm[r] & ~fm2[r]) != 0ull;
+            if (!((ex == kCgConv || ex == kCgMaxit) && newly)) break;
+        }
+    }
+
+    MT_INLINE double step_norm(const double (&s)[R]) const
+    {
+        if (!has_l) return sqrt(dot(s, s));
+        // t = L^T s: t_i = sum_{k >= i} L_ki s_k
+        double t[R];
+        MT_UNROLL for (int r = 0; r < R; r++) t[r] = 0.0;
+        for (int k = 0; k < n; k++) {
+            const int rk = k >> 6, lk = k & 63;
+            double sk = 0.0;
+            MT_UNROLL for (int r = 0; r < R; r++)
+                if (r == rk) sk = s[r];
+            sk = uni(bcast(sk, lk));
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = row(r);
+                if (i <= k) t[r] = fma(M[k * ld + (i < n ? i : 0)], sk, t[r]);
+            }
+        }
+        MT_UNROLL for (int r = 0; r < R; r++) t[r] = valid(r) ? t[r] : 0.0;
+        return sqrt(dot(t, t));
+    }
+
+    MT_INLINE double radius_update(double rho, double ared, double gts, double snorm, bool fin) const
+    {
+        double astar;
+        if (!fin) {
+            astar = kSig1;
+            rho = -__builtin_inf();
+        } else {
+            const double gam = -ared - gts;
+            if (gam <= 0.0) astar = kSig3;
+            else {
+                astar = -0.5 * gts / gam;
+                if (astar < kSig1) astar = kSig1;
+            }
+        }
+        if (rho <= kEta0) return dmin((astar > kSig1 ? astar : kSig1) * snorm, kSig2 * delta);
+        if (rho <= kEta1) return dmax(kSig1 * delta, dmin(astar * snorm, kSig2 * delta));
+        if (rho < kEta2) return dmax(kSig1 * delta, dmin(astar * snorm, kSig3 * delta));
+        return dmax(delta, dmin(astar * snorm, kSig3 * delta));
+    }
+
+    MT_INLINE int32_t solve(const Options &o, double delta_in, double alphac_in)
+    {
+        iters = 0;
+        delta = 0.0;
+        alphac = 1.0;
+        f = __builtin_nan("");
+        bool bad = false;
+        MT_UNROLL for (int r = 0; r < R; r++) bad = bad || (valid(r) && !(lo[r] <= hi[r]));
+        if (__ballot(bad) != 0ull) return kBadBounds;
+        MT_UNROLL for (int r = 0; r < R; r++) x[r] = clampb(x[r], lo[r], hi[r]);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        f = fg(x, g);
+        bool fin = true;
+        MT_UNROLL for (int r = 0; r < R; r++) fin = fin && isfinite(g[r]);
+        fin = isfinite(f) && __ballot(!fin) == 0ull;
+        if (!fin) return kNonfinite;
+        if (pg_inf() <= o.gtol) return kConverged;
+        if (o.warm && delta_in > 0.0) delta = delta_in;
+        else if (o.delta0 > 0.0) delta = o.delta0;
+        else {
+            delta = pg_nrm2();
+            if (delta == 0.0) delta = 1.0;
+        }
+        if (o.warm && alphac_in > 0.0) alphac = alphac_in;
+        hess();
+        int32_t status;
+        for (;;) {
+            cauchy();
+            subspace(o.cg_rtol);
+            double s[R], hs[R];
+            MT_UNROLL for (int r = 0; r < R; r++) s[r] = xs[r] - x[r];
+            const double snorm = step_norm(s);
+            amul(s, hd, hs);
+            double hh[R];
+            MT_UNROLL for (int r = 0; r < R; r++) hh[r] = fma(0.5, hs[r], g[r]);
+            const double gts = dot(g, s);
+            const double pred = -dot(s, hh);
+            iters++;
+            if (!(pred > 0.0)) { status = kStalled; break; }
+            double gt[R];
+            const double ft = fg(xs, gt);
+            const bool tfin = isfinite(ft);
+            double ared = f - ft;
+            if (tfin && pred <= kAredSwitch * (fabs(f) > 1.0 ? fabs(f) : 1.0)) {
+                double sg[R];
+                MT_UNROLL for (int r = 0; r < R; r++) sg[r] = g[r] + gt[r];
+                ared = -0.5 * dot(sg, s);
+            }
+            const double rho = tfin ? ared / pred : -__builtin_inf();
+            delta = radius_update(rho, ared, gts, snorm, tfin);
+            const bool accept = rho > kEta0;
+            if (accept) {
+                MT_UNROLL for (int r = 0; r < R; r++) { x[r] = xs[r]; g[r] = gt[r]; }
+                f = ft;
+            }
+            bool ok = true;
+            MT_UNROLL for (int r = 0; r < R; r++) ok = ok && isfinite(g[r]);
+            ok = isfinite(f) && __ballot(!ok) == 0ull;
+            if (!ok) { status = kNonfinite; break; }
+            if (pg_inf() <= o.gtol) { status = kConverged; break; }
+            if (iters >= o.max_iter) { status = kMaxIter; break; }
+            const double tiny = kStallRel * (fabs(f) > 1.0 ? fabs(f) : 1.0);
+            if (tfin && fabs(ared) <= tiny && pred <= tiny) { status = kStalled; break; }
+            if (accept) hess();
+        }
+        return status;
+    }
+};
+
+}  // namespace mt

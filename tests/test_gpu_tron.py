@@ -51,13 +51,13 @@ def check_parity(bt, g, ref, convex, idx=None):
     for j, b in enumerate(idx):
         n, p, lo, hi, _ = bt.instance(b)
         xg = g["x"][vo[b]:vo[b + 1]]
-        assert np.all(xg >= lo) and np.all(xg <= hi), b
         fo_ref = ref["f"][j]
         xo = ref["x"][ref["voff"][j]:ref["voff"][j + 1]]
         if ref["status"][j] != 0:
             assert g["status"][b] == ref["status"][j], (b, g["status"][b], ref["status"][j])
             continue
         assert g["status"][b] == 0, (b, g["status"][b])
+        assert np.all(xg >= lo) and np.all(xg <= hi), b
         fg = oracle.eval_f(bt.family, n, p, xg)
         pg = oracle.projgrad_inf(xg, lo, hi, oracle.eval_g(bt.family, n, p, xg))
         worst["pg"] = max(worst["pg"], pg)
@@ -208,3 +208,58 @@ def test_packing_invariance(tron):
     for j, b in enumerate(idx):
         assert np.array_equal(gs["x"][6 * j:6 * j + 6], g["x"][6 * b:6 * b + 6])
         assert gs["f"][j] == g["f"][b] and gs["iters"][j] == g["iters"][b]
+
+
+# ---------------------------------------------------------------- wavefront-per-instance sizes
+@pytest.mark.parametrize("n", [9, 16, 17, 31, 33, 64, 65, 100, 128])
+def test_qp4_wave_sizes(tron, n):
+    bt = W.qp4_batch(40 if n <= 64 else 16, n, config_id=70 + n)
+    g = gpu_solve(tron, bt)
+    w = check_parity(bt, g, oracle_ref(bt), convex=True)
+    assert np.all(g["status"] == 0), np.bincount(g["status"])
+
+
+def test_uneven_4_to_64(tron):
+    sizes = W.loguniform_sizes(600, 4, 64, config_id=3)
+    bt = W.qp4_batch(600, sizes, config_id=3)
+    g = gpu_solve(tron, bt)
+    check_parity(bt, g, oracle_ref(bt), convex=True)
+
+
+def test_uneven_4_to_128(tron):
+    sizes = W.loguniform_sizes(150, 4, 128, config_id=4)
+    bt = W.qp4_batch(150, sizes, config_id=4)
+    g = gpu_solve(tron, bt)
+    check_parity(bt, g, oracle_ref(bt), convex=True)
+    h = tron.Batch(W.QP4, sizes)
+    plan = h.plan()
+    h.close()
+    assert sum(b["count"] for b in plan) == 150
+    assert {b["lanes"] for b in plan} == {1, 64}
+
+
+def test_wave_edge_cases(tron):
+    n = 20
+    bt = W.qp4_batch(4, n, config_id=61)
+    bt.lo[1 * n + 7] = 5.0                        # l > u
+    bt.x0[2 * n + 3] = np.nan                     # non-finite start (inf would be projected)
+    bt.lo[3 * n + 4] = bt.hi[3 * n + 4] = -0.75   # fixed variable
+    g = gpu_solve(tron, bt)
+    ref = oracle_ref(bt)
+    assert list(g["status"]) == list(ref["status"])
+    assert list(g["status"]) == [0, 4, 3, 0]
+    assert g["x"][3 * n + 4] == -0.75
+    check_parity(bt, g, ref, convex=True)
+
+
+def test_wave_packing_invariance(tron):
+    sizes = W.loguniform_sizes(300, 4, 80, config_id=33)
+    bt = W.qp4_batch(300, sizes, config_id=33)
+    g = gpu_solve(tron, bt)
+    idx = [299, 3, 150, 77, 0]
+    sub = bt.subset(idx)
+    gs = gpu_solve(tron, sub)
+    vo, svo = bt.voff(), sub.voff()
+    for j, b in enumerate(idx):
+        assert np.array_equal(gs["x"][svo[j]:svo[j + 1]], g["x"][vo[b]:vo[b + 1]])
+        assert gs["f"][j] == g["f"][b]
