@@ -69,6 +69,200 @@ def cpu_baseline(bt, budget_s):
                 flops_per_instance=float(flops.mean()), status=r["status"])
 
 
+def time_solves(solve, steps, warmup, stream):
+    """Run `solve()` warmup + steps times; per-step HIP-event latency (ms) and wall time (s)."""
+    import torch
+    for _ in range(warmup):
+        solve()
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        starts[k].record(stream)
+        solve()
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return np.array([a.elapsed_time(b) for a, b in zip(starts, ends)]), total
+
+
+def bench_qp4(args):
+    """256 quartic problems, n = 8: the oracle's CPU seconds (1 thread and all threads) and the
+    GPU's time for the same batch."""
+    import torch
+    import oracle
+    from paper_2106_14995_amd import tron
+    from paper_2106_14995_amd import workloads as W
+    bt = W.qp4_batch(256, 8, config_id=0)
+    cpu = {}
+    for nt in (1, 0):
+        best = None
+        for _ in range(5):
+            t0 = time.perf_counter()
+            r = oracle.solve(bt, nthreads=nt, with_stats=False)
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        cpu["threads_%d" % (r["threads"])] = best
+    h = tron.Batch(W.QP4, 8, batch=256)
+    dev = tron.to_device(bt)
+    stream = torch.cuda.current_stream()
+    lat, total = time_solves(lambda: h.solve(*dev, stream=stream), args.steps, args.warmup, stream)
+    print(json.dumps({"config": "qp4 256 x n=8 (quartic, strictly convex), gtol 1e-6",
+                      "oracle_cpu_seconds": cpu, "gpu_ms_per_batch_p50": float(np.median(lat)),
+                      "gpu_ms_per_batch_p99": float(np.percentile(lat, 99)),
+                      "gpu_solves_per_s": 256 * args.steps / total}), flush=True)
+    h.close()
+
+
+def bench_uneven(args):
+    """50,000 quartic problems with n log-uniform in [4,64]: one bucketed solve (buckets run
+    concurrently, captured once in a graph and replayed) against one launch per distinct n on
+    one stream (the same kernels, each sized exactly for its n)."""
+    import torch
+    from paper_2106_14995_amd import tron
+    from paper_2106_14995_amd import workloads as W
+    B = args.batch if args.batch != 65536 else 50000
+    log(f"generating {B} uneven QP4 instances")
+    sizes = W.loguniform_sizes(B, 4, 64, config_id=3)
+    bt = W.qp4_batch(B, sizes, config_id=3)
+    stream = torch.cuda.current_stream()
+    dev = tron.to_device(bt)
+    out = dict(x=torch.empty(bt.n.astype(np.int64).sum(), dtype=torch.float64, device="cuda"),
+               f=torch.empty(B, dtype=torch.float64, device="cuda"),
+               status=torch.empty(B, dtype=torch.int32, device="cuda"),
+               iters=torch.empty(B, dtype=torch.int32, device="cuda"))
+    res = {"config": f"qp4 uneven, {B} instances, n log-uniform in [4,64], gtol 1e-6"}
+    for graph in (False, True):
+        h = tron.Batch(W.QP4, sizes, opts=tron.options(graph=graph))
+        lat, total = time_solves(lambda: h.solve(*dev, **out, stream=stream), args.steps, args.warmup, stream)
+        key = "bucketed_graph" if graph else "bucketed_streams"
+        res[key] = {"solves_per_s": B * args.steps / total, "p50_ms": float(np.median(lat)),
+                    "p99_ms": float(np.percentile(lat, 99)), "buckets": len(h.plan())}
+        if graph:
+            res["converged"] = int((out["status"] == 0).sum().item())
+        h.close()
+    # one launch per distinct n, serial on one stream
+    per = []
+    for k in np.unique(sizes):
+        idx = np.nonzero(sizes == k)[0]
+        sub = bt.subset(idx)
+        hk = tron.Batch(W.QP4, int(k), batch=len(idx))
+        dk = tron.to_device(sub)
+        per.append((hk, dk))
+    lat, total = time_solves(lambda: [hk.solve(*dk, stream=stream) for hk, dk in per],
+                             args.steps, args.warmup, stream)
+    res["one_launch_per_size"] = {"solves_per_s": B * args.steps / total, "p50_ms": float(np.median(lat)),
+                                  "p99_ms": float(np.percentile(lat, 99)), "launches": len(per)}
+    for hk, _ in per:
+        hk.close()
+    print(json.dumps(res), flush=True)
+
+
+def bench_admm(args):
+    """Component ADMM on the synthetic 2,000-bus network: time per iteration (all kernels,
+    including the 3,000 branch solves) and the residuals after the run."""
+    import torch
+    from paper_2106_14995_amd import tron
+    from paper_2106_14995_amd import workloads as W
+    net = W.network()
+    a = tron.Admm(net)
+    iters = 1000 if args.steps == 100 else args.steps
+    stream = torch.cuda.current_stream()
+    resid = torch.empty(2 * iters, dtype=torch.float64, device="cuda")
+    a.step(5)
+    torch.cuda.synchronize()
+    a.close()
+    a = tron.Admm(net)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a.step(iters, resid=resid, stream=stream)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    r = resid.view(iters, 2).cpu().numpy()
+    print(json.dumps({"config": "component ADMM, 2,000 buses, 3,000 branches, 500 generators, rho 400",
+                      "iterations": iters, "ms_per_iteration": 1e3 * total / iters,
+                      "branch_solves_per_s": net.nbranch * iters / total,
+                      "primal_residual_first_last": [float(r[0, 0]), float(r[-1, 0])],
+                      "dual_residual_first_last": [float(r[0, 1]), float(r[-1, 1])]}), flush=True)
+    a.close()
+
+
+def bench_serve(args):
+    """Serving: requests of B = round(exp(U[0, ln 4096])) quartic problems with n log-uniform
+    in [4,128], drawn as slices of a seeded pool. The saturated instance rate is measured with
+    every request submitted at once; then Poisson arrivals at 0.25/0.5/0.75/0.9 of that rate
+    (in requests/s = rate / E[B]) give per-request latency (submission to completion) and
+    throughput, for the continuous-batching server and for the naive FIFO configuration (one
+    request on the device at a time, one stream, no coalescing: a launch per size bucket per
+    request)."""
+    import math
+    import threading
+    from paper_2106_14995_amd import tron
+    from paper_2106_14995_amd import workloads as W
+    P = 12000
+    log(f"generating a pool of {P} instances, n log-uniform in [4,128]")
+    sizes = W.loguniform_sizes(P, 4, 128, config_id=4)
+    pool = W.qp4_batch(P, sizes, config_id=4)
+    vo, po = pool.voff(), pool.poff()
+    rng = np.random.default_rng(4)
+    R = args.requests
+
+    def make_requests(seed):
+        r = np.random.default_rng(seed)
+        out = []
+        for _ in range(R):
+            b = int(round(math.exp(r.uniform(0.0, math.log(4096)))))
+            b = max(1, min(b, 4096))
+            s0 = int(r.integers(0, P - b + 1))
+            out.append((pool.n[s0:s0 + b], pool.params[po[s0]:po[s0 + b]], pool.lo[vo[s0]:vo[s0 + b]],
+                        pool.hi[vo[s0]:vo[s0 + b]], pool.x0[vo[s0]:vo[s0 + b]]))
+        return out
+
+    reqs = make_requests(44)
+    mean_b = float(np.mean([len(q[0]) for q in reqs]))
+
+    def run(srv_kw, qps):
+        srv = tron.Server(W.QP4, **srv_kw)
+        t_arr = np.cumsum(rng.exponential(1.0 / qps, R)) if qps else np.zeros(R)
+        tickets = [None] * R
+        t0 = time.perf_counter()
+
+        def feeder():
+            for i, q in enumerate(reqs):
+                d = t0 + t_arr[i] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(*q)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        lat = np.empty(R)
+        for i, t in enumerate(tickets):
+            srv.wait(t)
+            lat[i] = srv.result(t)["latency"]
+        wall = time.perf_counter() - t0
+        inst = srv.stats()["instances"]
+        srv.close()
+        return dict(solves_per_s=inst / wall, p50_ms=1e3 * float(np.percentile(lat, 50)),
+                    p99_ms=1e3 * float(np.percentile(lat, 99)), wall_s=wall)
+
+    served = dict(hbm_budget=4 << 30, max_inflight=8, streams=4, coalesce=True)
+    naive = dict(hbm_budget=4 << 30, max_inflight=1, streams=1, coalesce=False)
+    log("saturation (all requests at once)")
+    sat = run(served, 0.0)
+    sat_naive = run(naive, 0.0)
+    res = {"config": f"serving: {R} requests per level, B log-uniform in [1,4096] (mean {mean_b:.0f}), "
+                     "n log-uniform in [4,128], quartic problems, gtol 1e-6",
+           "saturated": {"served": sat, "naive": sat_naive}, "levels": []}
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        qps = frac * sat["solves_per_s"] / mean_b
+        log(f"load {frac}: {qps:.0f} requests/s")
+        res["levels"].append({"load": frac, "qps": qps, "served": run(served, qps), "naive": run(naive, qps)})
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +275,13 @@ def main():
     ap.add_argument("--mode", default="br6", choices=["br6", "copy"],
                     help="copy: a plain device-to-device copy of known size, used to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--config", default="br6", choices=["br6", "qp4", "uneven", "admm", "serve"],
+                    help="br6: the headline batch (default); qp4: 256 x n=8 quartic problems "
+                         "(oracle CPU seconds and GPU time); uneven: 50,000 quartic problems with "
+                         "n log-uniform in [4,64], bucketed graph vs one launch per size; admm: "
+                         "the component ADMM on the 2,000-bus synthetic network; serve: Poisson "
+                         "stream of requests of 1-4,096 quartic problems, n log-uniform in [4,128]")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: requests per load level")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -103,6 +304,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read_per_copy": nbytes,
                           "bytes_written_per_copy": nbytes, "copies": args.steps}), flush=True)
+        return
+    if args.config != "br6":
+        {"qp4": bench_qp4, "uneven": bench_uneven, "admm": bench_admm, "serve": bench_serve}[args.config](args)
         return
     log(f"generating {args.batch} BR6 instances")
     bt = W.br6_batch(args.batch, config_id=1)

@@ -77,6 +77,10 @@ typedef struct {
 /* Start from the radius and Cauchy step length the handle kept from its previous solve
  * (per instance), instead of the cold rule. x0 is always the caller's. */
 #define TRON_FLAG_WARM 1u
+/* Capture the whole solve (all size buckets, forked over the handle's streams) into a HIP
+ * graph on the first call with a given set of pointers, and replay that graph on later calls
+ * with the same pointers (new pointers or options re-capture). */
+#define TRON_FLAG_GRAPH 2u
 
 void tron_default_options(tron_options *opt);
 const char *tron_last_error(void);
@@ -100,7 +104,9 @@ tron_err tron_batch_create(tron_batch **out, tron_family family, int64_t batch,
 /* Solve every instance (Algorithm 1 per instance). d_x0 (read) and d_x (written) may be the
  * same buffer for an in-place warm start. d_f (batch doubles), d_status and d_iters (batch
  * int32 each) are written. d_params, d_lo, d_hi are read only. Bounds may be +-inf.
- * Errors: INVALID (null pointers), DEVICE (launch failure). */
+ * Instances with n <= 8 are solved one per GPU lane, larger ones one per wavefront; the
+ * size buckets run concurrently on the handle's own streams, joined back into `stream`.
+ * Errors: INVALID (null pointers), DEVICE (launch or capture failure). */
 tron_err tron_batch_solve(tron_batch *h, const double *d_params, const double *d_lo,
                           const double *d_hi, const double *d_x0, double *d_x, double *d_f,
                           int32_t *d_status, int32_t *d_iters, void *stream);
@@ -126,6 +132,54 @@ tron_err tron_batch_set_timestamps(tron_batch *h, int64_t *d_ts);
 int64_t tron_clock_rate_hz(void);
 
 tron_err tron_batch_destroy(tron_batch *h);
+
+/* ------------------------------------------------------------------------------------ */
+/* Continuous-batching server. Solve requests (each a batch of instances of one family,   */
+/* sizes mixed, the same Algorithm 1 per instance) are queued from any host thread and    */
+/* admitted in arrival order as the device-memory budget and the in-flight LDS budget     */
+/* allow; consecutive queued requests share one launch group; groups run concurrently on   */
+/* the server's streams, so requests that arrive while others are on the GPU overlap with */
+/* them. An instance's result does not depend on what it was batched with.                */
+/* ------------------------------------------------------------------------------------ */
+typedef struct tron_server tron_server;
+
+typedef struct {
+    size_t hbm_budget;            /* device bytes for requests in flight and open sessions;
+                                     also the size of the pinned host staging area          */
+    size_t lds_budget;            /* LDS bytes of wavefront-kernel instances in flight      */
+    int32_t max_inflight;         /* launch groups on the device at once (>= 1)             */
+    int32_t streams;              /* device streams the groups are dealt to (>= 1)          */
+    int32_t coalesce;             /* 1: a launch group may take several queued requests     */
+    int32_t max_group_instances;  /* instances per launch group (>= 1)                      */
+    tron_options opt;             /* solver options of every request (flags ignored)        */
+} tron_server_config;
+
+void tron_server_default_config(tron_server_config *cfg);
+/* Allocates the device arena and pinned staging up front and starts the scheduler thread.
+ * Errors: INVALID (configuration), NOMEM, DEVICE. */
+tron_err tron_server_create(tron_server **out, tron_family family, const tron_server_config *cfg);
+/* Queue `batch` instances given as host arrays packed as for tron_batch_create (copied before
+ * the call returns). session != 0 keeps the instances' solution, radius and Cauchy step
+ * resident on the device after the solve; a later request of the same session (same sizes)
+ * may pass x0 = NULL to start from them. A session holds at most one request at a time.
+ * Errors: INVALID, BUSY (larger than the device budget, or its session is busy). */
+tron_err tron_server_submit(tron_server *s, int64_t batch, const int32_t *n, const double *params,
+                            const double *lo, const double *hi, const double *x0, uint64_t session,
+                            int64_t *ticket);
+/* *state: 0 queued, 1 on the device, 2 done. */
+tron_err tron_server_poll(tron_server *s, int64_t ticket, int32_t *state);
+/* Block until the request is done (timeout_s < 0: no limit); BUSY on timeout. */
+tron_err tron_server_wait(tron_server *s, int64_t ticket, double timeout_s);
+/* Copy a finished request's outputs to host arrays (any may be NULL) and release the ticket;
+ * latency_s is the time from submission to completion. BUSY if not finished. */
+tron_err tron_server_result(tron_server *s, int64_t ticket, double *x, double *f, int32_t *status,
+                            int32_t *iters, double *latency_s);
+/* Free a session's resident state (BUSY while it has a request outstanding). */
+tron_err tron_server_close_session(tron_server *s, uint64_t session);
+/* out4: requests done, instances done, device bytes in use, LDS bytes in flight. */
+tron_err tron_server_stats(tron_server *s, int64_t *out4);
+/* Stops the scheduler, waits for the groups on the device, frees everything. */
+tron_err tron_server_destroy(tron_server *s);
 
 /* ------------------------------------------------------------------------------------ */
 /* Component ADMM of the power-flow application (section 6.1).                           */

@@ -26,6 +26,15 @@ typedef void (*lane_launch_fn)(const LaneArgs &, hipStream_t);
 
 // Launch the BR6 lane kernel (n = 6) over a.count instances.
 void mt_launch_br6(const LaneArgs &a, hipStream_t st);
+// The lane kernel for (family, N <= 8), or null when unsupported.
+lane_launch_fn mt_lane_launcher(tron_family fam, int N);
+// The wavefront-per-instance kernel (QP4) for instances with n <= nmax (nmax <= 128);
+// LDS is sized for nmax.
+void mt_launch_wave(const LaneArgs &a, int nmax, hipStream_t st);
+// LDS bytes the wave kernel uses for one instance of size n (its bucket's footprint).
+size_t mt_wave_lds_bytes(int nmax);
+// Make the wave kernels accept the largest LDS request (once per process and device).
+void mt_prepare_wave_kernels();
 
 // Record an error message for tron_last_error() and return `code`.
 tron_err mt_fail(tron_err code, const char *fmt, ...);

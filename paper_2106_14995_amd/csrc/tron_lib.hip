@@ -182,12 +182,6 @@ static void launch_wave(const LaneArgs &a, int nmax, hipStream_t st)
 {
     if (a.count <= 0) return;
     const size_t lds = wave_lds_bytes(nmax);
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)wave_kernel<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)wave_lds_bytes(64 * R));
-        attr_set = true;
-    }
     hipLaunchKernelGGL((wave_kernel<R>), dim3((unsigned)a.count), dim3(64), lds, st, a);
 }
 
@@ -202,6 +196,21 @@ struct Bucket {
     lane_launch_fn lane;
 };
 
+lane_launch_fn mt_lane_launcher(tron_family fam, int N) { return lane_launcher(fam, N); }
+void mt_launch_wave(const LaneArgs &a, int nmax, hipStream_t st)
+{
+    if (nmax <= 64) launch_wave<1>(a, nmax, st);
+    else launch_wave<2>(a, nmax, st);
+}
+size_t mt_wave_lds_bytes(int nmax) { return wave_lds_bytes(nmax); }
+void mt_prepare_wave_kernels()
+{
+    (void)hipFuncSetAttribute((const void *)wave_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)wave_lds_bytes(64));
+    (void)hipFuncSetAttribute((const void *)wave_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)wave_lds_bytes(128));
+}
+
 static void launch_bucket(const Bucket &b, const LaneArgs &a, hipStream_t st)
 {
     if (b.lanes == 1) b.lane(a, st);
@@ -211,6 +220,8 @@ static void launch_bucket(const Bucket &b, const LaneArgs &a, hipStream_t st)
 
 // bucket of the wave kernel for n > 8: the next of 16, 32, 64, 128
 static int wave_nmax(int n) { return n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 128; }
+
+constexpr int kMaxSideStreams = 4;
 
 struct tron_batch {
     int device = 0;
@@ -224,7 +235,21 @@ struct tron_batch {
     int32_t *d_n = nullptr;
     int64_t *d_poff = nullptr, *d_voff = nullptr;
     std::vector<Bucket> buckets;
+    // buckets run concurrently on side streams, forked from and joined to the caller's
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> ev;          // ev[0]: fork; ev[1 + k]: join of side stream k
+    // captured solve (TRON_FLAG_GRAPH): replayed while the pointers stay the same
+    hipGraphExec_t graph = nullptr;
+    hipStream_t cap = nullptr;           // capture stream
+    const void *graph_key[9] = {};
 };
+
+static void drop_graph(tron_batch *h)
+{
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    h->graph = nullptr;
+    for (auto &k : h->graph_key) k = nullptr;
+}
 
 static mt::Options dev_options(const tron_options &o)
 {
@@ -240,6 +265,10 @@ static mt::Options dev_options(const tron_options &o)
 static void free_batch(tron_batch *h)
 {
     if (!h) return;
+    drop_graph(h);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
+    for (hipStream_t q : h->side) (void)hipStreamDestroy(q);
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     (void)hipFree(h->d_state);
     (void)hipFree(h->d_n);
     (void)hipFree(h->d_poff);
@@ -387,6 +416,22 @@ extern "C" tron_err tron_batch_create(tron_batch **out, tron_family fam, int64_t
     }
     rc = build_plan(h, n, st);
     if (rc != TRON_OK) return bail(rc);
+    if (h->buckets.size() > 1) {
+        const int k = (int)std::min<size_t>(h->buckets.size(), kMaxSideStreams);
+        for (int i = 0; i < k; i++) {
+            hipStream_t q;
+            if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess)
+                return bail(mt_fail(TRON_ERR_DEVICE, "stream creation failed"));
+            h->side.push_back(q);
+        }
+        for (int i = 0; i <= k; i++) {
+            hipEvent_t e;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+                return bail(mt_fail(TRON_ERR_DEVICE, "event creation failed"));
+            h->ev.push_back(e);
+        }
+    }
+    mt_prepare_wave_kernels();
     if (hipStreamSynchronize(st) != hipSuccess) return bail(mt_fail(TRON_ERR_DEVICE, "sync failed"));
     *out = h;
     return TRON_OK;
@@ -420,11 +465,66 @@ extern "C" tron_err tron_batch_solve(tron_batch *h, const double *d_params, cons
     a.n_uniform = h->n_uniform;
     a.psize = h->n_uniform ? (int32_t)tron_param_size(h->fam, h->n_uniform) : 0;
     a.opt = dev_options(h->opt);
-    for (const Bucket &b : h->buckets) {
-        a.index = b.d_index;
-        a.count = b.count;
-        launch_bucket(b, a, st);
+    const bool use_graph = (h->opt.flags & TRON_FLAG_GRAPH) != 0u;
+    const void *key[9] = {d_params, d_lo, d_hi, d_x0, d_x, d_f, d_status, d_iters, h->d_ts};
+    if (use_graph && h->graph && std::equal(key, key + 9, h->graph_key)) {
+        HIP_TRY(hipGraphLaunch(h->graph, st));
+        return TRON_OK;
     }
+    hipStream_t cs = st;  // where the launch sequence is enqueued (or captured)
+    if (use_graph) {
+        // capture on the handle's own stream (the caller's may be the null stream, which
+        // cannot be captured); the graph is then launched on the caller's stream
+        drop_graph(h);
+        if (!h->cap) HIP_TRY(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        cs = h->cap;
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    }
+    tron_err rc = TRON_OK;
+    if (h->side.empty()) {
+        for (const Bucket &b : h->buckets) {
+            a.index = b.d_index;
+            a.count = b.count;
+            launch_bucket(b, a, cs);
+        }
+    } else {
+        // fork: every side stream waits for the caller's stream; buckets are dealt to the
+        // side streams heaviest first; join: the caller's stream waits for all of them
+        const int k = (int)h->side.size();
+        if (hipEventRecord(h->ev[0], cs) != hipSuccess) rc = mt_fail(TRON_ERR_DEVICE, "event record failed");
+        for (int i = 0; i < k && rc == TRON_OK; i++)
+            if (hipStreamWaitEvent(h->side[i], h->ev[0], 0) != hipSuccess)
+                rc = mt_fail(TRON_ERR_DEVICE, "stream wait failed");
+        for (size_t i = 0; i < h->buckets.size() && rc == TRON_OK; i++) {
+            const Bucket &b = h->buckets[i];
+            a.index = b.d_index;
+            a.count = b.count;
+            launch_bucket(b, a, h->side[i % k]);
+        }
+        for (int i = 0; i < k && rc == TRON_OK; i++) {
+            if (hipEventRecord(h->ev[1 + i], h->side[i]) != hipSuccess ||
+                hipStreamWaitEvent(cs, h->ev[1 + i], 0) != hipSuccess)
+                rc = mt_fail(TRON_ERR_DEVICE, "join failed");
+        }
+    }
+    if (use_graph) {
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &g);
+        if (rc == TRON_OK && e != hipSuccess) rc = mt_fail(TRON_ERR_DEVICE, "capture failed: %s", hipGetErrorString(e));
+        if (rc == TRON_OK) {
+            e = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc = mt_fail(TRON_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+        }
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != TRON_OK) {
+            drop_graph(h);
+            return rc;
+        }
+        std::copy(key, key + 9, h->graph_key);
+        HIP_TRY(hipGraphLaunch(h->graph, st));
+        return TRON_OK;
+    }
+    if (rc != TRON_OK) return rc;
     HIP_TRY(hipGetLastError());
     return TRON_OK;
 }
@@ -452,6 +552,7 @@ extern "C" tron_err tron_batch_set_options(tron_batch *h, const tron_options *op
     if (!h || !opt) return mt_fail(TRON_ERR_INVALID, "null argument");
     if (check_options(*opt) != TRON_OK) return TRON_ERR_INVALID;
     h->opt = *opt;
+    drop_graph(h);
     return TRON_OK;
 }
 
@@ -472,6 +573,7 @@ extern "C" tron_err tron_batch_set_timestamps(tron_batch *h, int64_t *d_ts)
 {
     if (!h) return mt_fail(TRON_ERR_INVALID, "handle is null");
     h->d_ts = d_ts;
+    drop_graph(h);
     return TRON_OK;
 }
 

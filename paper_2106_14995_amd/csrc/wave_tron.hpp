@@ -18,10 +18,31 @@
 
 namespace mt {
 
+// DPP lane permutation within 16-lane rows (VALU only, no LDS traffic)
+template <int CTRL>
+MT_INLINE double dpp_mov(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kDppSwap1 = 0xB1;      // quad_perm [1,0,3,2]
+constexpr int kDppSwap2 = 0x4E;      // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141; // lane i <- 7 - i within 8 lanes
+constexpr int kDppMirror = 0x140;     // lane i <- 15 - i within 16 lanes
+
+MT_INLINE double bcast(double v, int src);
+
+// Sum over the 64 lanes; every lane returns the same bits: within each 16-lane row the
+// partners of every step are combined commutatively, and the four row sums are read back
+// and added in one fixed order.
 MT_INLINE double wave_sum(double v)
 {
-    MT_UNROLL for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-    return v;
+    v += dpp_mov<kDppSwap1>(v);
+    v += dpp_mov<kDppSwap2>(v);
+    v += dpp_mov<kDppHalfMirror>(v);
+    v += dpp_mov<kDppMirror>(v);
+    return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
 }
 
 // make a value the compiler treats as per-lane into a scalar (all lanes hold the same bits)
@@ -39,13 +60,15 @@ MT_INLINE double bcast(double v, int src)
     return __hiloint2double(hi, lo);
 }
 
+MT_INLINE double max_nan(double a, double b) { return (b > a || b != b) ? b : a; }  // NaN propagates
+
 MT_INLINE double wave_max(double v)
 {
-    MT_UNROLL for (int m = 32; m >= 1; m >>= 1) {
-        const double o = __shfl_xor(v, m);
-        v = (o > v || o != o) ? o : v;  // NaN propagates
-    }
-    return v;
+    v = max_nan(v, dpp_mov<kDppSwap1>(v));
+    v = max_nan(v, dpp_mov<kDppSwap2>(v));
+    v = max_nan(v, dpp_mov<kDppHalfMirror>(v));
+    v = max_nan(v, dpp_mov<kDppMirror>(v));
+    return max_nan(max_nan(bcast(v, 0), bcast(v, 16)), max_nan(bcast(v, 32), bcast(v, 48)));
 }
 
 // QP4 solved by one wave, R rows per lane (n <= 64 R).
@@ -71,25 +94,41 @@ struct WaveQP4 {
         return uni(wave_sum(s));
     }
 
-    // y = A v over the first n rows, A = H with diagonal diag (Q's or H's); rows >= n give 0
+    // H_kj for row k (< n) from the upper triangle, diag on the diagonal
+    MT_INLINE double hget(int k, int j, double dg) const
+    {
+        const double h = M[j < k ? j * ld + k : k * ld + j];
+        return j == k ? dg : h;
+    }
+
+    // y = A v over the first n rows, A = H with diagonal diag (Q's or H's); rows >= n give 0.
+    // Four independent accumulators per row; no lane-dependent branches in the loop.
     MT_INLINE void amul(const double (&v)[R], const double (&diag)[R], double (&y)[R]) const
     {
-        MT_UNROLL for (int r = 0; r < R; r++) y[r] = 0.0;
+        double acc[R][4];
+        int kk[R];
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
+            kk[r] = row(r) < n ? row(r) : 0;
+        }
         MT_UNROLL for (int rr = 0; rr < R; rr++) {
             const int jend = n - 64 * rr < 64 ? n - 64 * rr : 64;
-            for (int jj = 0; jj < jend; jj++) {
-                const int j = 64 * rr + jj;
+            int jj = 0;
+            for (; jj + 4 <= jend; jj += 4) {
+                double vj[4];
+                MT_UNROLL for (int u = 0; u < 4; u++) vj[u] = bcast(v[rr], jj + u);
+                MT_UNROLL for (int r = 0; r < R; r++)
+                    MT_UNROLL for (int u = 0; u < 4; u++)
+                        acc[r][u] = fma(hget(kk[r], 64 * rr + jj + u, diag[r]), vj[u], acc[r][u]);
+            }
+            for (; jj < jend; jj++) {
                 const double vj = bcast(v[rr], jj);
-                MT_UNROLL for (int r = 0; r < R; r++) {
-                    const int i = row(r);
-                    const int k = i < n ? i : 0;
-                    const double h0 = M[j < k ? j * ld + k : k * ld + j];  // H_kj from the upper triangle
-                    const double h = j == k ? diag[r] : h0;
-                    y[r] = fma(h, vj, y[r]);
-                }
+                MT_UNROLL for (int r = 0; r < R; r++)
+                    acc[r][0] = fma(hget(kk[r], 64 * rr + jj, diag[r]), vj, acc[r][0]);
             }
         }
-        MT_UNROLL for (int r = 0; r < R; r++) y[r] = valid(r) ? y[r] : 0.0;
+        MT_UNROLL for (int r = 0; r < R; r++)
+            y[r] = valid(r) ? (acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3]) : 0.0;
     }
 
     MT_INLINE void load(const double *__restrict__ p, const double *__restrict__ lop,
@@ -173,7 +212,16 @@ struct WaveQP4 {
                 if (k > j) a = M[j * ld + k];            // H_ij from the upper triangle
                 else a = hd[r] + alpha;                   // only used when i == j
                 if (fj && k >= j) {
-                    for (int q = 0; q < j; q++) a = fma(-M[k * ld + q], M[j * ld + q], a);
+                    // a -= L_k[0:j] . L_j[0:j], in 8 independent partial sums so the LDS
+                    // loads pipeline and the FMA chains are j/8 long
+                    const double *rk = M + k * ld, *rj = M + j * ld;
+                    double p[8] = {a, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                    int q = 0;
+                    for (; q + 8 <= j; q += 8) {
+                        MT_UNROLL for (int u = 0; u < 8; u++) p[u] = fma(-rk[q + u], rj[q + u], p[u]);
+                    }
+                    for (; q < j; q++) p[0] = fma(-rk[q], rj[q], p[0]);
+                    a = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
                 }
                 s[r] = a;
             }
@@ -233,19 +281,24 @@ struct WaveQP4 {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 
-    // L y = b in place (b zero outside the factored set stays zero)
+    // component j of b * dinv, taken from its owner lane (wave-uniform result)
+    MT_INLINE double owner_scaled(const double (&b)[R], int j) const
+    {
+        double v = b[0] * dinv[0];
+        MT_UNROLL for (int r = 1; r < R; r++) v = (j >> 6) == r ? b[r] * dinv[r] : v;
+        return bcast(v, j & 63);
+    }
+
+    // L y = b in place (b zero outside the factored set stays zero); branch-free steps
     MT_INLINE void fwd(double (&b)[R]) const
     {
         for (int j = 0; j < n; j++) {
-            const int rj = j >> 6, lj = j & 63;
-            double yj = 0.0;
-            MT_UNROLL for (int r = 0; r < R; r++)
-                if (r == rj) yj = b[r] * dinv[r];
-            yj = uni(bcast(yj, lj));
+            const double yj = owner_scaled(b, j);
             MT_UNROLL for (int r = 0; r < R; r++) {
                 const int i = row(r);
-                if (i == j) b[r] = yj;
-                else if (i > j && i < n) b[r] = fma(-M[i * ld + j], yj, b[r]);
+                const bool below = i > j && i < n;
+                const double l = M[below ? i * ld + j : 0];
+                b[r] = i == j ? yj : (below ? fma(-l, yj, b[r]) : b[r]);
             }
         }
     }
@@ -254,15 +307,12 @@ struct WaveQP4 {
     MT_INLINE void bwd(double (&b)[R]) const
     {
         for (int j = n - 1; j >= 0; j--) {
-            const int rj = j >> 6, lj = j & 63;
-            double yj = 0.0;
-            MT_UNROLL for (int r = 0; r < R; r++)
-                if (r == rj) yj = b[r] * dinv[r];
-            yj = uni(bcast(yj, lj));
+            const double yj = owner_scaled(b, j);
             MT_UNROLL for (int r = 0; r < R; r++) {
                 const int i = row(r);
-                if (i == j) b[r] = yj;
-                else if (i < j) b[r] = fma(-M[j * ld + i], yj, b[r]);
+                const bool above = i < j;
+                const double l = M[above ? j * ld + i : 0];
+                b[r] = i == j ? yj : (above ? fma(-l, yj, b[r]) : b[r]);
             }
         }
     }
@@ -435,14 +485,14 @@ struct WaveQP4 {
         double t[R];
         MT_UNROLL for (int r = 0; r < R; r++) t[r] = 0.0;
         for (int k = 0; k < n; k++) {
-            const int rk = k >> 6, lk = k & 63;
-            double sk = 0.0;
-            MT_UNROLL for (int r = 0; r < R; r++)
-                if (r == rk) sk = s[r];
-            sk = uni(bcast(sk, lk));
+            double sk = s[0];
+            MT_UNROLL for (int r = 1; r < R; r++) sk = (k >> 6) == r ? s[r] : sk;
+            sk = bcast(sk, k & 63);
             MT_UNROLL for (int r = 0; r < R; r++) {
                 const int i = row(r);
-                if (i <= k) t[r] = fma(M[k * ld + (i < n ? i : 0)], sk, t[r]);
+                const bool in = i <= k;
+                const double l = M[in ? k * ld + i : 0];
+                t[r] = in ? fma(l, sk, t[r]) : t[r];
             }
         }
         MT_UNROLL for (int r = 0; r < R; r++) t[r] = valid(r) ? t[r] : 0.0;

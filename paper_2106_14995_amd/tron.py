@@ -16,6 +16,7 @@ from . import build as _build
 QP4, BR6, HS45M = 0, 1, 2
 CONVERGED, MAX_ITER, STALLED, NONFINITE, BAD_BOUNDS = 0, 1, 2, 3, 4
 FLAG_WARM = 1
+FLAG_GRAPH = 2
 ERRORS = {1: "invalid argument", 2: "out of memory", 3: "device error", 4: "unsupported",
           5: "busy"}
 
@@ -31,6 +32,12 @@ class Options(C.Structure):
                 ("cg_rtol", C.c_double), ("delta0", C.c_double)]
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("lds_budget", C.c_size_t), ("max_inflight", C.c_int32),
+                ("streams", C.c_int32), ("coalesce", C.c_int32), ("max_group_instances", C.c_int32),
+                ("opt", Options)]
+
+
 class NetworkC(C.Structure):
     _fields_ = [("nbus", C.c_int32), ("nbranch", C.c_int32), ("ngen", C.c_int32),
                 ("ref_bus", C.c_int32), ("rho", C.c_double), ("base_mva", C.c_double),
@@ -44,7 +51,9 @@ EXPORTS = ("tron_default_options", "tron_last_error", "tron_param_size", "tron_b
            "tron_batch_solve", "tron_batch_get_state", "tron_batch_set_state",
            "tron_batch_set_options", "tron_batch_plan", "tron_batch_destroy",
            "admm_state_size", "admm_create", "admm_step", "admm_get_state", "admm_set_state",
-           "admm_destroy")
+           "admm_destroy", "tron_server_default_config", "tron_server_create", "tron_server_submit",
+           "tron_server_poll", "tron_server_wait", "tron_server_result", "tron_server_close_session",
+           "tron_server_stats", "tron_server_destroy", "tron_batch_set_timestamps", "tron_clock_rate_hz")
 
 
 def lib_path() -> str:
@@ -70,6 +79,17 @@ def lib():
         L.tron_batch_set_options.argtypes = [P, C.POINTER(Options)]
         L.tron_batch_plan.argtypes = [P, P, P, I32]
         L.tron_batch_destroy.argtypes = [P]
+        L.tron_clock_rate_hz.restype = I64
+        L.tron_batch_set_timestamps.argtypes = [P, P]
+        L.tron_server_default_config.argtypes = [C.POINTER(ServerConfig)]
+        L.tron_server_create.argtypes = [C.POINTER(P), I32, C.POINTER(ServerConfig)]
+        L.tron_server_submit.argtypes = [P, I64, P, P, P, P, P, C.c_uint64, C.POINTER(I64)]
+        L.tron_server_poll.argtypes = [P, I64, C.POINTER(I32)]
+        L.tron_server_wait.argtypes = [P, I64, C.c_double]
+        L.tron_server_result.argtypes = [P, I64, P, P, P, P, C.POINTER(C.c_double)]
+        L.tron_server_close_session.argtypes = [P, C.c_uint64]
+        L.tron_server_stats.argtypes = [P, P]
+        L.tron_server_destroy.argtypes = [P]
         if hasattr(L, "admm_state_size"):
             L.admm_state_size.restype = I64
             L.admm_state_size.argtypes = [C.POINTER(NetworkC)]
@@ -87,11 +107,11 @@ def _check(rc):
         raise TronError(rc, lib().tron_last_error().decode())
 
 
-def options(gtol=1e-6, max_iter=500, cg_rtol=0.1, delta0=0.0, warm=False) -> Options:
+def options(gtol=1e-6, max_iter=500, cg_rtol=0.1, delta0=0.0, warm=False, graph=False) -> Options:
     o = Options()
     lib().tron_default_options(C.byref(o))
     o.gtol, o.max_iter, o.cg_rtol, o.delta0 = gtol, max_iter, cg_rtol, delta0
-    o.flags = FLAG_WARM if warm else 0
+    o.flags = (FLAG_WARM if warm else 0) | (FLAG_GRAPH if graph else 0)
     return o
 
 
@@ -245,6 +265,78 @@ class Admm:
     def close(self):
         if self._h:
             lib().admm_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A tron_server: continuous batching of solve requests given as host arrays."""
+
+    def __init__(self, family: int, hbm_budget=1 << 30, lds_budget=None, max_inflight=8, streams=4,
+                 coalesce=True, max_group_instances=65536, opts: Options | None = None):
+        L = lib()
+        cfg = ServerConfig()
+        L.tron_server_default_config(C.byref(cfg))
+        cfg.hbm_budget = int(hbm_budget)
+        if lds_budget is not None:
+            cfg.lds_budget = int(lds_budget)
+        cfg.max_inflight, cfg.streams = int(max_inflight), int(streams)
+        cfg.coalesce, cfg.max_group_instances = int(bool(coalesce)), int(max_group_instances)
+        if opts is not None:
+            cfg.opt = opts
+        self.family = int(family)
+        self._h = C.c_void_p()
+        self._sizes = {}
+        _check(L.tron_server_create(C.byref(self._h), self.family, C.byref(cfg)))
+
+    def submit(self, n, params, lo, hi, x0=None, session=0) -> int:
+        n = np.ascontiguousarray(n, dtype=np.int32)
+        arr = lambda a: None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+        params, lo, hi, x0 = arr(params), arr(lo), arr(hi), arr(x0)
+        p = lambda a: None if a is None or a.size == 0 else a.ctypes.data_as(C.c_void_p)
+        t = C.c_int64()
+        _check(lib().tron_server_submit(self._h, int(n.shape[0]), n.ctypes.data_as(C.c_void_p),
+                                        p(params), p(lo), p(hi), p(x0), C.c_uint64(session), C.byref(t)))
+        self._sizes[t.value] = (int(n.shape[0]), int(n.astype(np.int64).sum()))
+        return t.value
+
+    def submit_batch(self, batch, x0=True, session=0) -> int:
+        return self.submit(batch.n, batch.params, batch.lo, batch.hi, batch.x0 if x0 else None, session)
+
+    def poll(self, ticket) -> int:
+        st = C.c_int32()
+        _check(lib().tron_server_poll(self._h, ticket, C.byref(st)))
+        return st.value
+
+    def wait(self, ticket, timeout=-1.0):
+        _check(lib().tron_server_wait(self._h, ticket, float(timeout)))
+
+    def result(self, ticket):
+        B, nsum = self._sizes.pop(ticket)
+        x = np.empty(nsum); f = np.empty(B)
+        st = np.empty(B, dtype=np.int32); it = np.empty(B, dtype=np.int32)
+        lat = C.c_double()
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check(lib().tron_server_result(self._h, ticket, p(x), p(f), p(st), p(it), C.byref(lat)))
+        return dict(x=x, f=f, status=st, iters=it, latency=lat.value)
+
+    def close_session(self, session):
+        _check(lib().tron_server_close_session(self._h, C.c_uint64(session)))
+
+    def stats(self):
+        out = np.zeros(4, dtype=np.int64)
+        _check(lib().tron_server_stats(self._h, out.ctypes.data_as(C.c_void_p)))
+        return dict(requests=int(out[0]), instances=int(out[1]), device_bytes=int(out[2]),
+                    lds_inflight=int(out[3]))
+
+    def close(self):
+        if self._h:
+            lib().tron_server_destroy(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

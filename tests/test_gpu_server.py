@@ -1,0 +1,130 @@
+"""GPU tests of the continuous-batching server (tron_server_* in include/tron.h).
+
+The instances of a request are solved by the same kernels as the batch API, one instance per
+lane or per wavefront, with nothing shared between instances; so a request's results are
+compared bitwise between "alone" and "in a mix" (the stated tolerance is exact equality),
+and against the oracle with the parity bars of test_gpu_tron."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2106_14995_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def T():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2106_14995_amd import tron
+    tron.lib()
+    return tron
+
+
+def mixed(count, cfg, nmax=100):
+    sizes = W.loguniform_sizes(count, 2, nmax, config_id=cfg)
+    return W.qp4_batch(count, sizes, config_id=cfg)
+
+
+def test_alone_equals_mix_and_batch_api(T):
+    import torch
+    probe = mixed(300, 80)
+    others = [mixed(int(k), 81 + i) for i, k in enumerate([700, 3, 1200, 64, 1, 500, 250, 2000])]
+    srv = T.Server(W.QP4, hbm_budget=1 << 30, max_inflight=6, streams=4)
+    t = srv.submit_batch(probe)
+    srv.wait(t)
+    alone = srv.result(t)
+    # the same request in the middle of a stream of others, submitted from two threads
+    tickets = {}
+
+    def feed(lst, tag):
+        for j, b in enumerate(lst):
+            tickets[(tag, j)] = srv.submit_batch(b)
+
+    th = threading.Thread(target=feed, args=(others[:4], "a"))
+    th.start()
+    tp = srv.submit_batch(probe)
+    feed(others[4:], "b")
+    th.join()
+    srv.wait(tp)
+    mix = srv.result(tp)
+    for k in tickets.values():
+        srv.wait(k)
+        srv.result(k)
+    srv.close()
+    for key in ("x", "f", "status", "iters"):
+        assert np.array_equal(alone[key], mix[key]), key
+    # the batch API gives the same bits
+    h = T.Batch(W.QP4, probe.n)
+    x, f, st, it = h.solve(*T.to_device(probe))
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy(), alone["x"])
+    assert np.array_equal(st.cpu().numpy(), alone["status"])
+    h.close()
+
+
+def test_server_matches_oracle(T):
+    bt = mixed(200, 82, nmax=128)
+    srv = T.Server(W.QP4)
+    t = srv.submit_batch(bt)
+    srv.wait(t)
+    r = srv.result(t)
+    srv.close()
+    ref = oracle.solve(bt)
+    vo = bt.voff()
+    assert np.all(r["status"] == 0)
+    for b in range(bt.batch):
+        n, p, lo, hi, _ = bt.instance(b)
+        xg = r["x"][vo[b]:vo[b + 1]]
+        assert oracle.projgrad_inf(xg, lo, hi, oracle.eval_g(0, n, p, xg)) <= 1e-6
+        assert abs(oracle.eval_f(0, n, p, xg) - ref["f"][b]) <= 1e-8 * max(1, abs(ref["f"][b]))
+    assert r["latency"] > 0
+
+
+def test_session_warm_start(T):
+    bt = mixed(150, 83)
+    srv = T.Server(W.QP4)
+    t1 = srv.submit_batch(bt, session=7)
+    srv.wait(t1)
+    r1 = srv.result(t1)
+    with pytest.raises(T.TronError):
+        srv.close_session(12345)
+    # from the resident solution: converged before any iteration, same point
+    t2 = srv.submit_batch(bt, x0=False, session=7)
+    srv.wait(t2)
+    r2 = srv.result(t2)
+    assert np.all(r2["status"] == 0) and np.all(r2["iters"] == 0)
+    assert np.array_equal(r2["x"], r1["x"])
+    srv.close_session(7)
+    srv.close()
+
+
+def test_admission_under_a_tight_budget(T):
+    small = [mixed(40, 90 + i, nmax=40) for i in range(12)]
+    srv = T.Server(W.QP4, hbm_budget=1 << 20, max_inflight=4, streams=2)
+    too_big = mixed(3000, 95, nmax=128)
+    with pytest.raises(T.TronError) as e:
+        srv.submit_batch(too_big)
+    assert e.value.code == 5  # BUSY: can never fit
+    tickets = [srv.submit_batch(b) for b in small]
+    peak = 0
+    while any(srv.poll(t) != 2 for t in tickets):
+        peak = max(peak, srv.stats()["device_bytes"])
+        time.sleep(0.0005)
+    assert peak <= 1 << 20
+    for t, b in zip(tickets, small):
+        r = srv.result(t)
+        assert np.all(r["status"] == 0)
+    assert srv.stats()["requests"] == len(small)
+    srv.close()
+
+
+def test_destroy_with_work_pending(T):
+    srv = T.Server(W.QP4, max_inflight=2)
+    for i in range(6):
+        srv.submit_batch(mixed(500, 100 + i))
+    srv.close()  # waits for what is on the device, drops the queue, returns

@@ -263,3 +263,35 @@ def test_wave_packing_invariance(tron):
     for j, b in enumerate(idx):
         assert np.array_equal(gs["x"][svo[j]:svo[j + 1]], g["x"][vo[b]:vo[b + 1]])
         assert gs["f"][j] == g["f"][b]
+
+
+def test_graph_replays_match_eager(tron):
+    """The captured, bucket-concurrent solve replays to the same bits as the eager solve, with
+    the program's own eager work and synchronisations between replays."""
+    import torch
+    sizes = W.loguniform_sizes(900, 2, 72, config_id=34)
+    bt = W.qp4_batch(900, sizes, config_id=34)
+    dev = tron.to_device(bt)
+    eager = tron.Batch(W.QP4, sizes)
+    xe, fe, se, ie = [t.clone() for t in eager.solve(*dev)]
+    torch.cuda.synchronize()
+    g = tron.Batch(W.QP4, sizes, opts=tron.options(graph=True))
+    x = torch.empty_like(xe); f = torch.empty_like(fe)
+    st = torch.empty_like(se); it = torch.empty_like(ie)
+    for rep in range(4):
+        x.fill_(-7.0); f.zero_(); st.fill_(-1); it.fill_(-1)
+        g.solve(*dev, x=x, f=f, status=st, iters=it)
+        torch.cuda.synchronize()
+        assert torch.equal(x, xe) and torch.equal(f, fe), rep
+        assert torch.equal(st, se) and torch.equal(it, ie), rep
+        # eager work of the program between replays
+        eager.solve(*dev)
+        _ = (x * 2).sum().item()
+        torch.cuda.synchronize()
+    # new output pointers: the graph is captured again and still matches
+    x2 = torch.empty_like(xe)
+    g.solve(*dev, x=x2, f=f, status=st, iters=it)
+    torch.cuda.synchronize()
+    assert torch.equal(x2, xe)
+    g.close()
+    eager.close()
