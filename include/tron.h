@@ -101,6 +101,37 @@ tron_err tron_batch_create(tron_batch **out, tron_family family, int64_t batch,
                            const int32_t *n_host, int32_t n_uniform, const tron_options *opt,
                            void *stream);
 
+/* Launch plan of a handle: instances with n <= lane_max_n are solved one per GPU lane (a
+ * kernel per exact n); larger ones one per wavefront, grouped into buckets by the first of
+ * `edges` (increasing, <= 128) that holds them, with LDS sized for that edge. Buckets run
+ * concurrently on `streams` streams; lane kernels use workgroups of lane_block (64 or 256). */
+typedef struct {
+    int32_t lane_max_n;   /* 0..8 */
+    int32_t nedges;       /* 1..16 */
+    int32_t edges[16];
+    int32_t streams;      /* 1..8 */
+    int32_t lane_block;   /* 64 or 256 */
+} tron_plan_spec;
+
+/* lane_max_n 8, edges 16/32/64/128, 4 streams, lane_block 256. */
+void tron_default_plan_spec(tron_plan_spec *spec);
+/* tron_batch_create with an explicit plan (spec NULL = default). INVALID for a bad spec,
+ * UNSUPPORTED when some n exceeds the largest edge. */
+tron_err tron_batch_create_ex(tron_batch **out, tron_family family, int64_t batch,
+                              const int32_t *n_host, int32_t n_uniform, const tron_options *opt,
+                              const tron_plan_spec *spec, void *stream);
+/* Autotuner: time candidate plans (bucket edge sets, streams, lane/wave split, lane
+ * workgroup size) on the caller's own batch, `reps` timed solves each after one warm-up, and
+ * return the fastest in *best (and its time per solve in *best_ms). The outputs are written
+ * by the trial solves. When cache_path is not NULL the result is looked up in / appended to
+ * that text file, keyed by the family and the histogram of sizes (a cached entry returns
+ * without timing). Errors as tron_batch_create / solve, plus DEVICE for timing failures. */
+tron_err tron_autotune(tron_family family, int64_t batch, const int32_t *n_host,
+                       const double *d_params, const double *d_lo, const double *d_hi,
+                       const double *d_x0, double *d_x, double *d_f, int32_t *d_status,
+                       int32_t *d_iters, int32_t reps, const char *cache_path,
+                       tron_plan_spec *best, double *best_ms, void *stream);
+
 /* Solve every instance (Algorithm 1 per instance). d_x0 (read) and d_x (written) may be the
  * same buffer for an in-place warm start. d_f (batch doubles), d_status and d_iters (batch
  * int32 each) are written. d_params, d_lo, d_hi are read only. Bounds may be +-inf.

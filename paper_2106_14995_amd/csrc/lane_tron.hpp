@@ -51,17 +51,19 @@ enum : int { kCgConv = 0, kCgMaxit = 1, kCgNeg = 2, kCgBnd = 3 };
 // packed lower-triangular index, row by row
 MT_INLINE constexpr int tri(int i, int j) { return i >= j ? i * (i + 1) / 2 + j : j * (j + 1) / 2 + i; }
 
+// projection onto [lo, hi] that keeps a NaN (used on the caller's x0)
 MT_INLINE double clampb(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+// projection for finite v (two min/max instructions; used once x and g are known finite)
+MT_INLINE double clampf(double v, double lo, double hi) { return fmin(fmax(v, lo), hi); }
 MT_INLINE double dmax(double a, double b) { return a > b ? a : b; }
 MT_INLINE double dmin(double a, double b) { return a < b ? a : b; }
 
-// projected-gradient component (section 5.1): g inside, min(g,0) at l, max(g,0) at u, 0 if l = u
+// projected-gradient component (section 5.1): g inside, min(g,0) at l, max(g,0) at u, 0 if
+// l = u; g is finite wherever this is called (finiteness is checked first)
 MT_INLINE double pg_comp(double x, double lo, double hi, double g)
 {
-    if (lo == hi) return 0.0;
-    if (x <= lo) return g < 0.0 ? g : 0.0;
-    if (x >= hi) return g > 0.0 ? g : 0.0;
-    return g;
+    const double v = x <= lo ? fmin(g, 0.0) : (x >= hi ? fmax(g, 0.0) : g);
+    return lo == hi ? 0.0 : v;
 }
 
 struct Options {
@@ -316,10 +318,7 @@ struct LaneTron {
     MT_INLINE double pg_inf() const
     {
         double m = 0.0;
-        MT_UNROLL for (int i = 0; i < N; i++) {
-            const double v = fabs(pg_comp(x[i], lo[i], hi[i], g[i]));
-            if (!(v <= m)) m = v;
-        }
+        MT_UNROLL for (int i = 0; i < N; i++) m = fmax(m, fabs(pg_comp(x[i], lo[i], hi[i], g[i])));
         return m;
     }
     MT_INLINE double pg_nrm2() const
@@ -366,7 +365,7 @@ struct LaneTron {
         cauchy_trials++;
         double st[N];
         MT_UNROLL for (int i = 0; i < N; i++) {
-            xt[i] = clampb(fma(-a, g[i], x[i]), lo[i], hi[i]);
+            xt[i] = clampf(fma(-a, g[i], x[i]), lo[i], hi[i]);
             st[i] = xt[i] - x[i];
         }
         if (!(dot(st, st) <= delta * delta)) return false;  // ||s|| <= delta
@@ -546,7 +545,7 @@ struct LaneTron {
                 search_trials++;
                 double d[N], hd[N];
                 MT_UNROLL for (int i = 0; i < N; i++) {
-                    xt[i] = clampb(fma(beta, w[i], xs[i]), lo[i], hi[i]);
+                    xt[i] = clampf(fma(beta, w[i], xs[i]), lo[i], hi[i]);
                     d[i] = xt[i] - xs[i];
                 }
                 hmul(d, hd);

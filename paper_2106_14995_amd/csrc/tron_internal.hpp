@@ -19,6 +19,7 @@ struct LaneArgs {
     int64_t *ts;             // optional: per-instance start / end device clock (2 per instance)
     int64_t count, batch;
     int32_t n_uniform, psize;
+    int32_t lane_block;      // workgroup size of the lane kernels (64 or 256; 0 means 256)
     mt::Options opt;
 };
 

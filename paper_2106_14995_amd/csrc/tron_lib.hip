@@ -5,6 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -14,6 +17,8 @@
 #include "tron.h"
 #include "tron_internal.hpp"
 #include "wave_tron.hpp"
+
+constexpr int kMaxSideStreams = 4;
 
 // ------------------------------------------------------------------------------------
 // error reporting
@@ -60,7 +65,7 @@ constexpr int kLaneBlock = 256;
 template <class F, int N>
 __global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a)
 {
-    const int64_t t = (int64_t)blockIdx.x * kLaneBlock + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.count) return;
     const int64_t b = a.index ? (int64_t)a.index[t] : t;
     const int n = a.nper ? a.nper[b] : a.n_uniform;
@@ -98,8 +103,9 @@ __global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a)
 template <class F, int N>
 static void launch_lane(const LaneArgs &a, hipStream_t st)
 {
-    const unsigned grid = (unsigned)((a.count + kLaneBlock - 1) / kLaneBlock);
-    if (grid) hipLaunchKernelGGL((lane_kernel<F, N>), dim3(grid), dim3(kLaneBlock), 0, st, a);
+    const int blk = a.lane_block == 64 ? 64 : kLaneBlock;
+    const unsigned grid = (unsigned)((a.count + blk - 1) / blk);
+    if (grid) hipLaunchKernelGGL((lane_kernel<F, N>), dim3(grid), dim3(blk), 0, st, a);
 }
 
 static lane_launch_fn lane_launcher(tron_family fam, int N)
@@ -218,13 +224,39 @@ static void launch_bucket(const Bucket &b, const LaneArgs &a, hipStream_t st)
     else launch_wave<2>(a, b.nmax, st);
 }
 
-// bucket of the wave kernel for n > 8: the next of 16, 32, 64, 128
-static int wave_nmax(int n) { return n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 128; }
+static void default_spec(tron_plan_spec *p)
+{
+    p->lane_max_n = 8;
+    p->nedges = 4;
+    const int e[4] = {16, 32, 64, 128};
+    for (int i = 0; i < 16; i++) p->edges[i] = i < 4 ? e[i] : 0;
+    p->streams = kMaxSideStreams;
+    p->lane_block = 256;
+}
 
-constexpr int kMaxSideStreams = 4;
+static tron_err check_spec(const tron_plan_spec &p)
+{
+    if (p.lane_max_n < 0 || p.lane_max_n > 8 || p.nedges < 1 || p.nedges > 16 || p.streams < 1 ||
+        p.streams > 8 || (p.lane_block != 64 && p.lane_block != 256))
+        return mt_fail(TRON_ERR_INVALID, "invalid plan spec");
+    for (int i = 0; i < p.nedges; i++)
+        if (p.edges[i] < 1 || p.edges[i] > 128 || (i > 0 && p.edges[i] <= p.edges[i - 1]))
+            return mt_fail(TRON_ERR_INVALID, "plan edges must increase within 1..128");
+    return TRON_OK;
+}
+
+// wave bucket of size n under the spec: the first edge >= n (0 if none)
+static int spec_edge(const tron_plan_spec &p, int n)
+{
+    for (int i = 0; i < p.nedges; i++)
+        if (n <= p.edges[i]) return p.edges[i];
+    return 0;
+}
+
 
 struct tron_batch {
     int device = 0;
+    tron_plan_spec spec{};
     tron_family fam = TRON_FAMILY_QP4;
     int64_t batch = 0;
     int32_t n_uniform = 0;     // 0 when sizes differ
@@ -286,24 +318,25 @@ static tron_err check_options(const tron_options &o)
 
 // Buckets of the lane kernel: instances grouped by the smallest supported kernel size
 // that holds them (sizes 1..8 each get their own kernel).
-// Launch plan: n <= 8 goes to the lane kernel of exactly that n (one instance per lane);
-// larger n to the wave kernel of the next size in 16, 32, 64, 128 (one instance per
-// wavefront, LDS sized for the bucket), with the bucket's instances ordered largest first
-// so the longest solves start earliest. Heaviest buckets are launched first.
+// Launch plan: n <= spec.lane_max_n goes to the lane kernel of exactly that n (one
+// instance per lane); larger n to the wave kernel of the first spec edge >= n (one instance
+// per wavefront, LDS sized for the edge), each bucket ordered largest first. Wave buckets
+// (heaviest) are listed first so they start first.
 static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStream_t st)
 {
     if (h->batch == 0) return TRON_OK;
+    const tron_plan_spec &sp = h->spec;
+    auto lane_ok = [&](int k) { return k <= sp.lane_max_n && lane_launcher(h->fam, k) != nullptr; };
     if (h->n_uniform) {
         Bucket b{};
         b.count = h->batch;
         b.d_index = nullptr;
-        if (h->n_uniform <= 8) {
+        if (lane_ok(h->n_uniform)) {
             b.nmax = h->n_uniform;
             b.lanes = 1;
             b.lane = lane_launcher(h->fam, h->n_uniform);
-            if (!b.lane) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d not supported for this family", h->n_uniform);
         } else {
-            if (h->fam != TRON_FAMILY_QP4) return mt_fail(TRON_ERR_UNSUPPORTED, "n > 8 needs QP4");
+            if (h->fam != TRON_FAMILY_QP4) return mt_fail(TRON_ERR_UNSUPPORTED, "this family has no wave kernel");
             b.nmax = h->n_uniform;
             b.lanes = 64;
             b.lane = nullptr;
@@ -312,13 +345,14 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
         return TRON_OK;
     }
     std::vector<std::vector<int32_t>> lane_lists(9);
-    std::vector<std::vector<int32_t>> wave_lists(4);  // 16, 32, 64, 128
+    std::map<int, std::vector<int32_t>> wave_lists;  // edge -> instances
     for (int64_t i = 0; i < h->batch; i++) {
-        if (n[i] <= 8) lane_lists[n[i]].push_back((int32_t)i);
+        if (lane_ok(n[i])) lane_lists[n[i]].push_back((int32_t)i);
         else {
-            if (h->fam != TRON_FAMILY_QP4) return mt_fail(TRON_ERR_UNSUPPORTED, "n > 8 needs QP4");
-            const int w = wave_nmax(n[i]);
-            wave_lists[w == 16 ? 0 : w == 32 ? 1 : w == 64 ? 2 : 3].push_back((int32_t)i);
+            if (h->fam != TRON_FAMILY_QP4) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d has no kernel for this family", n[i]);
+            const int e = spec_edge(sp, n[i]);
+            if (!e) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d above the largest plan edge", n[i]);
+            wave_lists[e].push_back((int32_t)i);
         }
     }
     auto add = [&](std::vector<int32_t> &list, int nmax, int lanes) -> tron_err {
@@ -327,17 +361,15 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
         b.lanes = lanes;
         b.count = (int64_t)list.size();
         b.lane = lanes == 1 ? lane_launcher(h->fam, nmax) : nullptr;
-        if (lanes == 1 && !b.lane) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d not supported for this family", nmax);
         HIP_TRY(hipMalloc(&b.d_index, sizeof(int32_t) * list.size()));
         HIP_TRY(hipMemcpyAsync(b.d_index, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, st));
         h->buckets.push_back(b);
         return TRON_OK;
     };
-    for (int w = 3; w >= 0; w--) {
-        auto &list = wave_lists[w];
-        if (list.empty()) continue;
+    for (auto it = wave_lists.rbegin(); it != wave_lists.rend(); ++it) {
+        auto &list = it->second;
         std::stable_sort(list.begin(), list.end(), [&](int32_t a, int32_t b) { return n[a] > n[b]; });
-        tron_err rc = add(list, 16 << w, 64);
+        tron_err rc = add(list, it->first, 64);
         if (rc != TRON_OK) return rc;
     }
     for (int k = 8; k >= 1; k--) {
@@ -350,10 +382,34 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
     return TRON_OK;
 }
 
+extern "C" void tron_default_plan_spec(tron_plan_spec *spec)
+{
+    if (spec) default_spec(spec);
+}
+
+extern "C" tron_err tron_batch_create_ex(tron_batch **out, tron_family fam, int64_t batch,
+                                         const int32_t *n_host, int32_t n_uniform,
+                                         const tron_options *opt, const tron_plan_spec *spec,
+                                         void *stream);
+
 extern "C" tron_err tron_batch_create(tron_batch **out, tron_family fam, int64_t batch,
                                       const int32_t *n_host, int32_t n_uniform,
                                       const tron_options *opt, void *stream)
 {
+    return tron_batch_create_ex(out, fam, batch, n_host, n_uniform, opt, nullptr, stream);
+}
+
+extern "C" tron_err tron_batch_create_ex(tron_batch **out, tron_family fam, int64_t batch,
+                                         const int32_t *n_host, int32_t n_uniform,
+                                         const tron_options *opt, const tron_plan_spec *spec,
+                                         void *stream)
+{
+    tron_plan_spec sp;
+    default_spec(&sp);
+    if (spec) {
+        sp = *spec;
+        if (check_spec(sp) != TRON_OK) return TRON_ERR_INVALID;
+    }
     if (!out) return mt_fail(TRON_ERR_INVALID, "out is null");
     *out = nullptr;
     if (batch < 0 || batch > (int64_t)INT32_MAX) return mt_fail(TRON_ERR_INVALID, "batch out of range");
@@ -383,6 +439,7 @@ extern "C" tron_err tron_batch_create(tron_batch **out, tron_family fam, int64_t
     if (!h) return mt_fail(TRON_ERR_NOMEM, "host allocation failed");
     (void)hipGetDevice(&h->device);
     h->fam = fam;
+    h->spec = sp;
     h->batch = batch;
     h->n_uniform = uni;
     h->opt = o;
@@ -416,8 +473,8 @@ extern "C" tron_err tron_batch_create(tron_batch **out, tron_family fam, int64_t
     }
     rc = build_plan(h, n, st);
     if (rc != TRON_OK) return bail(rc);
-    if (h->buckets.size() > 1) {
-        const int k = (int)std::min<size_t>(h->buckets.size(), kMaxSideStreams);
+    if (h->buckets.size() > 1 && sp.streams > 1) {
+        const int k = (int)std::min<size_t>(h->buckets.size(), (size_t)sp.streams);
         for (int i = 0; i < k; i++) {
             hipStream_t q;
             if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess)
@@ -465,6 +522,7 @@ extern "C" tron_err tron_batch_solve(tron_batch *h, const double *d_params, cons
     a.n_uniform = h->n_uniform;
     a.psize = h->n_uniform ? (int32_t)tron_param_size(h->fam, h->n_uniform) : 0;
     a.opt = dev_options(h->opt);
+    a.lane_block = h->spec.lane_block;
     const bool use_graph = (h->opt.flags & TRON_FLAG_GRAPH) != 0u;
     const void *key[9] = {d_params, d_lo, d_hi, d_x0, d_x, d_f, d_status, d_iters, h->d_ts};
     if (use_graph && h->graph && std::equal(key, key + 9, h->graph_key)) {
@@ -588,5 +646,135 @@ extern "C" int64_t tron_clock_rate_hz(void)
 extern "C" tron_err tron_batch_destroy(tron_batch *h)
 {
     free_batch(h);
+    return TRON_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// autotuner
+// ------------------------------------------------------------------------------------
+static std::string tune_key(tron_family fam, int64_t batch, const int32_t *n)
+{
+    // family, batch, and the share of instances per size class (exact n <= 8, then octaves)
+    int64_t cls[13] = {0};
+    for (int64_t i = 0; i < batch; i++) {
+        const int k = n[i];
+        const int c = k <= 8 ? k : k <= 16 ? 9 : k <= 32 ? 10 : k <= 64 ? 11 : 12;
+        cls[c]++;
+    }
+    std::ostringstream o;
+    o << "fam=" << (int)fam << " batch=" << batch << " hist=";
+    for (int c = 1; c <= 12; c++) o << (c > 1 ? "," : "") << (batch ? (100 * cls[c] + batch / 2) / batch : 0);
+    return o.str();
+}
+
+static std::string spec_str(const tron_plan_spec &p)
+{
+    std::ostringstream o;
+    o << p.lane_max_n << " " << p.streams << " " << p.lane_block << " " << p.nedges;
+    for (int i = 0; i < p.nedges; i++) o << " " << p.edges[i];
+    return o.str();
+}
+
+static bool spec_parse(const std::string &t, tron_plan_spec *p)
+{
+    std::istringstream in(t);
+    tron_plan_spec q{};
+    if (!(in >> q.lane_max_n >> q.streams >> q.lane_block >> q.nedges)) return false;
+    if (q.nedges < 1 || q.nedges > 16) return false;
+    for (int i = 0; i < q.nedges; i++)
+        if (!(in >> q.edges[i])) return false;
+    if (check_spec(q) != TRON_OK) return false;
+    *p = q;
+    return true;
+}
+
+extern "C" tron_err tron_autotune(tron_family fam, int64_t batch, const int32_t *n_host,
+                                  const double *d_params, const double *d_lo, const double *d_hi,
+                                  const double *d_x0, double *d_x, double *d_f, int32_t *d_status,
+                                  int32_t *d_iters, int32_t reps, const char *cache_path,
+                                  tron_plan_spec *best, double *best_ms, void *stream)
+{
+    if (!n_host || !best || batch <= 0 || reps < 1) return mt_fail(TRON_ERR_INVALID, "bad argument");
+    hipStream_t st = (hipStream_t)stream;
+    const std::string key = tune_key(fam, batch, n_host);
+    if (cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        while (std::getline(in, line)) {
+            const size_t bar = line.find('|');
+            if (bar != std::string::npos && line.substr(0, bar) == key && spec_parse(line.substr(bar + 1), best)) {
+                if (best_ms) *best_ms = -1.0;
+                return TRON_OK;
+            }
+        }
+    }
+    int nmax = 0;
+    for (int64_t i = 0; i < batch; i++) nmax = std::max(nmax, n_host[i]);
+    const std::vector<std::vector<int>> edge_sets = {
+        {16, 32, 64, 128}, {32, 64, 128}, {12, 16, 24, 32, 48, 64, 96, 128},
+        {16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128}};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto time_spec = [&](const tron_plan_spec &sp, double *ms) -> tron_err {
+        tron_batch *h = nullptr;
+        tron_err rc = tron_batch_create_ex(&h, fam, batch, n_host, 0, nullptr, &sp, stream);
+        if (rc != TRON_OK) return rc;
+        rc = tron_batch_solve(h, d_params, d_lo, d_hi, d_x0, d_x, d_f, d_status, d_iters, stream);
+        float best_t = 1e30f;
+        for (int r = 0; r < reps && rc == TRON_OK; r++) {
+            if (hipEventRecord(e0, st) != hipSuccess) rc = mt_fail(TRON_ERR_DEVICE, "event");
+            if (rc == TRON_OK) rc = tron_batch_solve(h, d_params, d_lo, d_hi, d_x0, d_x, d_f, d_status, d_iters, stream);
+            if (rc == TRON_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rc = mt_fail(TRON_ERR_DEVICE, "event");
+            float t = 0.0f;
+            if (rc == TRON_OK && hipEventElapsedTime(&t, e0, e1) == hipSuccess) best_t = std::min(best_t, t);
+        }
+        tron_batch_destroy(h);
+        *ms = best_t;
+        return rc;
+    };
+    tron_plan_spec cur;
+    default_spec(&cur);
+    double cur_ms = 1e30;
+    tron_err rc = TRON_OK;
+    // stage 1: bucket edges x streams
+    for (const auto &es : edge_sets) {
+        for (int streams : {1, 4}) {
+            tron_plan_spec sp;
+            default_spec(&sp);
+            sp.nedges = (int)es.size();
+            for (int i = 0; i < sp.nedges; i++) sp.edges[i] = es[i];
+            sp.streams = streams;
+            if (spec_edge(sp, nmax) == 0 && nmax > sp.lane_max_n) continue;
+            double ms = 0.0;
+            rc = time_spec(sp, &ms);
+            if (rc != TRON_OK) break;
+            if (ms < cur_ms) { cur_ms = ms; cur = sp; }
+        }
+        if (rc != TRON_OK) break;
+    }
+    // stage 2: lane/wave split and lane workgroup size on the best edges
+    for (int lane_max : {4, 6, 8}) {
+        for (int blk : {64, 256}) {
+            if (rc != TRON_OK) break;
+            tron_plan_spec sp = cur;
+            sp.lane_max_n = lane_max;
+            sp.lane_block = blk;
+            if (lane_max == cur.lane_max_n && blk == cur.lane_block) continue;
+            double ms = 0.0;
+            rc = time_spec(sp, &ms);
+            if (rc == TRON_OK && ms < cur_ms) { cur_ms = ms; cur = sp; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != TRON_OK) return rc;
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    if (cache_path) {
+        std::ofstream out(cache_path, std::ios::app);
+        if (out) out << key << "|" << spec_str(cur) << "\n";
+    }
     return TRON_OK;
 }

@@ -178,10 +178,7 @@ struct WaveQP4 {
     MT_INLINE double pg_inf() const
     {
         double m = 0.0;
-        MT_UNROLL for (int r = 0; r < R; r++) {
-            const double v = valid(r) ? fabs(pg_comp(x[r], lo[r], hi[r], g[r])) : 0.0;
-            m = (!(v <= m)) ? v : m;
-        }
+        MT_UNROLL for (int r = 0; r < R; r++) m = fmax(m, valid(r) ? fabs(pg_comp(x[r], lo[r], hi[r], g[r])) : 0.0);
         return uni(wave_max(m));
     }
 
@@ -332,7 +329,7 @@ struct WaveQP4 {
     {
         double st[R], hs[R];
         MT_UNROLL for (int r = 0; r < R; r++) {
-            xt[r] = clampb(fma(-a, g[r], x[r]), lo[r], hi[r]);
+            xt[r] = clampf(fma(-a, g[r], x[r]), lo[r], hi[r]);
             st[r] = xt[r] - x[r];
         }
         if (!(dot(st, st) <= delta * delta)) return false;
@@ -458,7 +455,7 @@ struct WaveQP4 {
             for (int t = 0; t <= kSearchHalvings; t++) {
                 double d[R], hdv[R];
                 MT_UNROLL for (int r = 0; r < R; r++) {
-                    xt[r] = clampb(fma(beta, w[r], xs[r]), lo[r], hi[r]);
+                    xt[r] = clampf(fma(beta, w[r], xs[r]), lo[r], hi[r]);
                     d[r] = xt[r] - xs[r];
                 }
                 amul(d, hd, hdv);

@@ -32,6 +32,15 @@ class Options(C.Structure):
                 ("cg_rtol", C.c_double), ("delta0", C.c_double)]
 
 
+class PlanSpec(C.Structure):
+    _fields_ = [("lane_max_n", C.c_int32), ("nedges", C.c_int32), ("edges", C.c_int32 * 16),
+                ("streams", C.c_int32), ("lane_block", C.c_int32)]
+
+    def describe(self):
+        return dict(lane_max_n=self.lane_max_n, edges=list(self.edges[:self.nedges]),
+                    streams=self.streams, lane_block=self.lane_block)
+
+
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("lds_budget", C.c_size_t), ("max_inflight", C.c_int32),
                 ("streams", C.c_int32), ("coalesce", C.c_int32), ("max_group_instances", C.c_int32),
@@ -53,7 +62,8 @@ EXPORTS = ("tron_default_options", "tron_last_error", "tron_param_size", "tron_b
            "admm_state_size", "admm_create", "admm_step", "admm_get_state", "admm_set_state",
            "admm_destroy", "tron_server_default_config", "tron_server_create", "tron_server_submit",
            "tron_server_poll", "tron_server_wait", "tron_server_result", "tron_server_close_session",
-           "tron_server_stats", "tron_server_destroy", "tron_batch_set_timestamps", "tron_clock_rate_hz")
+           "tron_server_stats", "tron_server_destroy", "tron_batch_set_timestamps", "tron_clock_rate_hz",
+           "tron_default_plan_spec", "tron_batch_create_ex", "tron_autotune")
 
 
 def lib_path() -> str:
@@ -79,6 +89,11 @@ def lib():
         L.tron_batch_set_options.argtypes = [P, C.POINTER(Options)]
         L.tron_batch_plan.argtypes = [P, P, P, I32]
         L.tron_batch_destroy.argtypes = [P]
+        L.tron_default_plan_spec.argtypes = [C.POINTER(PlanSpec)]
+        L.tron_batch_create_ex.argtypes = [C.POINTER(P), I32, I64, P, I32, C.POINTER(Options),
+                                           C.POINTER(PlanSpec), P]
+        L.tron_autotune.argtypes = [I32, I64, P, P, P, P, P, P, P, P, P, I32, C.c_char_p,
+                                    C.POINTER(PlanSpec), C.POINTER(C.c_double), P]
         L.tron_clock_rate_hz.restype = I64
         L.tron_batch_set_timestamps.argtypes = [P, P]
         L.tron_server_default_config.argtypes = [C.POINTER(ServerConfig)]
@@ -142,7 +157,7 @@ class Batch:
     """A tron_batch handle: `batch` instances of `family` with sizes `n` (int or array)."""
 
     def __init__(self, family: int, n, batch: int | None = None, opts: Options | None = None,
-                 stream=None):
+                 stream=None, spec: "PlanSpec | None" = None):
         L = lib()
         if np.isscalar(n):
             if batch is None:
@@ -159,8 +174,9 @@ class Batch:
         self.psum = int(sum(param_size(family, int(v)) * int(c) for v, c in zip(vals, cnts)))
         self._h = C.c_void_p()
         o = opts if opts is not None else options()
-        _check(L.tron_batch_create(C.byref(self._h), self.family, self.batch, nptr, nuni,
-                                   C.byref(o), _stream_ptr(stream)))
+        _check(L.tron_batch_create_ex(C.byref(self._h), self.family, self.batch, nptr, nuni,
+                                      C.byref(o), C.byref(spec) if spec is not None else None,
+                                      _stream_ptr(stream)))
 
     def solve(self, params, lo, hi, x0, x=None, f=None, status=None, iters=None, stream=None):
         import torch
@@ -344,3 +360,27 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def plan_spec(lane_max_n=8, edges=(16, 32, 64, 128), streams=4, lane_block=256) -> PlanSpec:
+    p = PlanSpec()
+    p.lane_max_n, p.nedges, p.streams, p.lane_block = lane_max_n, len(edges), streams, lane_block
+    for i, e in enumerate(edges):
+        p.edges[i] = int(e)
+    return p
+
+
+def autotune(family, n, params, lo, hi, x0, x, f, status, iters, reps=3, cache_path=None,
+             stream=None):
+    """Time candidate plans on this batch (the C autotuner) and return (PlanSpec, ms per
+    solve; -1 when read from the cache)."""
+    import torch
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    best = PlanSpec()
+    ms = C.c_double()
+    ptr = lambda t: C.c_void_p(t.data_ptr()) if t is not None and t.numel() else None
+    _check(lib().tron_autotune(family, int(n.shape[0]), n.ctypes.data_as(C.c_void_p), ptr(params),
+                               ptr(lo), ptr(hi), ptr(x0), ptr(x), ptr(f), ptr(status), ptr(iters),
+                               int(reps), cache_path.encode() if cache_path else None,
+                               C.byref(best), C.byref(ms), _stream_ptr(stream)))
+    return best, ms.value

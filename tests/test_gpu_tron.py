@@ -295,3 +295,36 @@ def test_graph_replays_match_eager(tron):
     assert torch.equal(x2, xe)
     g.close()
     eager.close()
+
+
+def test_plan_specs_and_autotune(tron, tmp_path):
+    """Every plan (edges, lane/wave split, streams, lane workgroup size) meets the parity bars
+    (a plan only changes where an instance runs), and the autotuner returns a valid plan and
+    caches it."""
+    import torch
+    sizes = W.loguniform_sizes(700, 2, 90, config_id=35)
+    bt = W.qp4_batch(700, sizes, config_id=35)
+    dev = tron.to_device(bt)
+    ref = oracle_ref(bt)
+    for spec in (tron.plan_spec(), tron.plan_spec(lane_max_n=4, edges=(12, 24, 48, 96), streams=1,
+                                                  lane_block=64),
+                 tron.plan_spec(lane_max_n=0, edges=(8, 16, 32, 64, 128), streams=2)):
+        h = tron.Batch(W.QP4, sizes, spec=spec)
+        x, f, st, it = h.solve(*dev)
+        torch.cuda.synchronize()
+        g = dict(x=x.cpu().numpy(), f=f.cpu().numpy(), status=st.cpu().numpy(), iters=it.cpu().numpy())
+        h.close()
+        check_parity(bt, g, ref, convex=True)
+    with pytest.raises(tron.TronError):
+        tron.Batch(W.QP4, sizes, spec=tron.plan_spec(edges=(16, 32, 64)))  # 90 above the last edge
+    x = torch.empty(int(bt.n.sum()), dtype=torch.float64, device="cuda")
+    f = torch.empty(700, dtype=torch.float64, device="cuda")
+    st = torch.empty(700, dtype=torch.int32, device="cuda")
+    it = torch.empty(700, dtype=torch.int32, device="cuda")
+    cache = str(tmp_path / "tune.txt")
+    best, ms = tron.autotune(W.QP4, sizes, *dev, x, f, st, it, reps=1, cache_path=cache)
+    assert ms > 0 and best.nedges >= 1
+    best2, ms2 = tron.autotune(W.QP4, sizes, *dev, x, f, st, it, reps=1, cache_path=cache)
+    assert ms2 == -1.0 and best2.describe() == best.describe()
+    h = tron.Batch(W.QP4, sizes, spec=best)
+    h.close()
