@@ -374,6 +374,16 @@ def main():
     lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])  # ms per launch
     log(f"timed {args.steps} steps in {total:.3f} s; launch ms p50 {np.median(lat):.4f}")
 
+    # per-instance solve latency from device timestamps (one more solve, outside the timing)
+    ts = torch.zeros(2 * B, dtype=torch.int64, device="cuda")
+    tron.lib().tron_batch_set_timestamps(h._h, tron.C.c_void_p(ts.data_ptr()))
+    h.solve(params, lo, hi, x0, x, f, st, it, stream=stream)
+    torch.cuda.synchronize()
+    tron.lib().tron_batch_set_timestamps(h._h, None)
+    rate = float(tron.lib().tron_clock_rate_hz())
+    tsn = ts.cpu().numpy().reshape(B, 2).astype(np.float64)
+    inst_us = (tsn[:, 1] - tsn[:, 0]) / rate * 1e6 if rate > 0 else np.zeros(B)
+
     result = {
         "metric": "TRON subproblem solves/sec at 1e-6 proj-grad tol; p50/p99 solve latency",
         "value": B * args.steps / total,
@@ -384,6 +394,9 @@ def main():
         "ms_per_step": 1e3 * total / args.steps,
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
+        "instance_latency_us": {"p50": float(np.percentile(inst_us, 50)),
+                                "p99": float(np.percentile(inst_us, 99)),
+                                "max": float(inst_us.max())},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
