@@ -200,14 +200,14 @@ def bench_admm(args):
 
 def bench_hs45m(args):
     """The paper's kernel-design workload: 10,000 identical modified-hs45 problems
-    (f = 120 - prod x_i, 0 <= x_i <= i, x0_i = i/2), one batch per step, n = 2..8. The paper's
+    (f = 120 - prod x_i, 0 <= x_i <= i, x0_i = i/2), one batch per step, n = 1..32. The paper's
     Table 3 reports 9.536 ms per batch on one V100 with shared memory, n unstated (context)."""
     import torch
     from paper_2106_14995_amd import tron
     from paper_2106_14995_amd import workloads as W
     stream = torch.cuda.current_stream()
     rows = []
-    for n in range(2, 9):
+    for n in range(1, 33):
         bt = W.hs45m_batch(10000, n)
         h = tron.Batch(W.HS45M, n, batch=10000)
         dev = tron.to_device(bt)
@@ -318,8 +318,8 @@ def main():
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per load level")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the instances are independent; see the sharding notes in DESIGN.md)",
+        print("bench.py runs on one GPU only: there is no multi-GPU path here (the instances "
+              "are independent, so a multi-GPU run would split the batch by instance)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -63,7 +63,7 @@ enum {
  *          penalties of the eight couplings, [34..35] penalties of the two z couplings;
  *          flows per eqs. pij..qji with w = v^2, wR = v_i v_j cos(th_i - th_j),
  *          wI = v_i v_j sin(th_i - th_j).
- *   HS45M: 0 -- f = 120 - prod x_i (the variant of hs45 in section 4.2). 1 <= n <= 8. */
+ *   HS45M: 0 -- f = 120 - prod x_i (the variant of hs45 in section 4.2). 1 <= n <= 128. */
 typedef enum { TRON_FAMILY_QP4 = 0, TRON_FAMILY_BR6 = 1, TRON_FAMILY_HS45M = 2 } tron_family;
 
 typedef struct {

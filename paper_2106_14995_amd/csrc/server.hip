@@ -307,7 +307,7 @@ tron_err launch_group(tron_server *s, Group *g)
             if (!fn) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d unsupported", b.nmax);
             fn(a, st);
         } else {
-            mt_launch_wave(a, b.nmax, st);
+            mt_launch_wave(s->fam, a, b.nmax, st);
         }
     }
     HIP_TRY(hipGetLastError());

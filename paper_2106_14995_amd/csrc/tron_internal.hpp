@@ -29,9 +29,9 @@ typedef void (*lane_launch_fn)(const LaneArgs &, hipStream_t);
 void mt_launch_br6(const LaneArgs &a, hipStream_t st);
 // The lane kernel for (family, N <= 8), or null when unsupported.
 lane_launch_fn mt_lane_launcher(tron_family fam, int N);
-// The wavefront-per-instance kernel (QP4) for instances with n <= nmax (nmax <= 128);
-// LDS is sized for nmax.
-void mt_launch_wave(const LaneArgs &a, int nmax, hipStream_t st);
+// The wavefront-per-instance kernel of the family (QP4 or HS45M) for instances with
+// n <= nmax (nmax <= 128); LDS is sized for nmax.
+void mt_launch_wave(tron_family fam, const LaneArgs &a, int nmax, hipStream_t st);
 // LDS bytes the wave kernel uses for one instance of size n (its bucket's footprint).
 size_t mt_wave_lds_bytes(int nmax);
 // Make the wave kernels accept the largest LDS request (once per process and device).

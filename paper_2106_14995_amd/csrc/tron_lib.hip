@@ -53,7 +53,7 @@ extern "C" int64_t tron_param_size(tron_family fam, int32_t n)
 {
     if (fam == TRON_FAMILY_QP4 && n >= 1 && n <= 128) return (int64_t)n * (n + 1) / 2 + n + 1;
     if (fam == TRON_FAMILY_BR6 && n == 6) return 36;
-    if (fam == TRON_FAMILY_HS45M && n >= 1 && n <= 8) return 0;
+    if (fam == TRON_FAMILY_HS45M && n >= 1 && n <= 128) return 0;
     return -1;
 }
 
@@ -142,10 +142,10 @@ static lane_launch_fn lane_launcher(tron_family fam, int N)
 void mt_launch_br6(const LaneArgs &a, hipStream_t st) { launch_lane<mt::BR6, 6>(a, st); }
 
 // ------------------------------------------------------------------------------------
-// wavefront-per-instance kernels (8 < n <= 128, QP4); one 64-lane workgroup per instance,
-// so the hardware dispatcher hands the next instance to whichever CU frees up first
+// wavefront-per-instance kernels (8 < n <= 128; QP4 and HS45M); one 64-lane workgroup per
+// instance, so the hardware dispatcher hands the next instance to whichever CU frees up first
 // ------------------------------------------------------------------------------------
-template <int R>
+template <class Fam>
 __global__ __launch_bounds__(64) void wave_kernel(LaneArgs a)
 {
     extern __shared__ double smem[];
@@ -156,7 +156,8 @@ __global__ __launch_bounds__(64) void wave_kernel(LaneArgs a)
     const int64_t po = a.poff ? a.poff[b] : b * (int64_t)a.psize;
     const int64_t vo = a.voff ? a.voff[b] : b * (int64_t)n;
     const int64_t t0 = a.ts ? (int64_t)wall_clock64() : 0;
-    mt::WaveQP4<R> s;
+    constexpr int R = Fam::R;
+    mt::WaveTron<Fam> s;
     s.n = n;
     s.ld = n | 1;
     s.lane = threadIdx.x;
@@ -183,13 +184,28 @@ __global__ __launch_bounds__(64) void wave_kernel(LaneArgs a)
 
 static size_t wave_lds_bytes(int nmax) { return sizeof(double) * (size_t)nmax * (size_t)(nmax | 1); }
 
-template <int R>
+template <class Fam>
 static void launch_wave(const LaneArgs &a, int nmax, hipStream_t st)
 {
     if (a.count <= 0) return;
     const size_t lds = wave_lds_bytes(nmax);
-    hipLaunchKernelGGL((wave_kernel<R>), dim3((unsigned)a.count), dim3(64), lds, st, a);
+    hipLaunchKernelGGL((wave_kernel<Fam>), dim3((unsigned)a.count), dim3(64), lds, st, a);
 }
+
+// the wave kernel of the family for instances with n <= nmax (nmax <= 128)
+static void launch_wave_fam(tron_family fam, const LaneArgs &a, int nmax, hipStream_t st)
+{
+    using namespace mt;
+    if (fam == TRON_FAMILY_HS45M) {
+        if (nmax <= 64) launch_wave<WaveFamHS45M<1>>(a, nmax, st);
+        else launch_wave<WaveFamHS45M<2>>(a, nmax, st);
+    } else {
+        if (nmax <= 64) launch_wave<WaveFamQP4<1>>(a, nmax, st);
+        else launch_wave<WaveFamQP4<2>>(a, nmax, st);
+    }
+}
+
+static bool has_wave_kernel(tron_family fam) { return fam == TRON_FAMILY_QP4 || fam == TRON_FAMILY_HS45M; }
 
 // ------------------------------------------------------------------------------------
 // batch handle
@@ -203,25 +219,25 @@ struct Bucket {
 };
 
 lane_launch_fn mt_lane_launcher(tron_family fam, int N) { return lane_launcher(fam, N); }
-void mt_launch_wave(const LaneArgs &a, int nmax, hipStream_t st)
+void mt_launch_wave(tron_family fam, const LaneArgs &a, int nmax, hipStream_t st)
 {
-    if (nmax <= 64) launch_wave<1>(a, nmax, st);
-    else launch_wave<2>(a, nmax, st);
+    launch_wave_fam(fam, a, nmax, st);
 }
 size_t mt_wave_lds_bytes(int nmax) { return wave_lds_bytes(nmax); }
 void mt_prepare_wave_kernels()
 {
-    (void)hipFuncSetAttribute((const void *)wave_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)wave_lds_bytes(64));
-    (void)hipFuncSetAttribute((const void *)wave_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)wave_lds_bytes(128));
+    using namespace mt;
+    const int big = (int)wave_lds_bytes(128), small = (int)wave_lds_bytes(64);
+    (void)hipFuncSetAttribute((const void *)wave_kernel<WaveFamQP4<1>>, hipFuncAttributeMaxDynamicSharedMemorySize, small);
+    (void)hipFuncSetAttribute((const void *)wave_kernel<WaveFamQP4<2>>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    (void)hipFuncSetAttribute((const void *)wave_kernel<WaveFamHS45M<1>>, hipFuncAttributeMaxDynamicSharedMemorySize, small);
+    (void)hipFuncSetAttribute((const void *)wave_kernel<WaveFamHS45M<2>>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
-static void launch_bucket(const Bucket &b, const LaneArgs &a, hipStream_t st)
+static void launch_bucket(tron_family fam, const Bucket &b, const LaneArgs &a, hipStream_t st)
 {
     if (b.lanes == 1) b.lane(a, st);
-    else if (b.nmax <= 64) launch_wave<1>(a, b.nmax, st);
-    else launch_wave<2>(a, b.nmax, st);
+    else launch_wave_fam(fam, a, b.nmax, st);
 }
 
 static void default_spec(tron_plan_spec *p)
@@ -336,7 +352,7 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
             b.lanes = 1;
             b.lane = lane_launcher(h->fam, h->n_uniform);
         } else {
-            if (h->fam != TRON_FAMILY_QP4) return mt_fail(TRON_ERR_UNSUPPORTED, "this family has no wave kernel");
+            if (!has_wave_kernel(h->fam)) return mt_fail(TRON_ERR_UNSUPPORTED, "this family has no wave kernel");
             b.nmax = h->n_uniform;
             b.lanes = 64;
             b.lane = nullptr;
@@ -349,7 +365,7 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
     for (int64_t i = 0; i < h->batch; i++) {
         if (lane_ok(n[i])) lane_lists[n[i]].push_back((int32_t)i);
         else {
-            if (h->fam != TRON_FAMILY_QP4) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d has no kernel for this family", n[i]);
+            if (!has_wave_kernel(h->fam)) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d has no kernel for this family", n[i]);
             const int e = spec_edge(sp, n[i]);
             if (!e) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d above the largest plan edge", n[i]);
             wave_lists[e].push_back((int32_t)i);
@@ -543,7 +559,7 @@ extern "C" tron_err tron_batch_solve(tron_batch *h, const double *d_params, cons
         for (const Bucket &b : h->buckets) {
             a.index = b.d_index;
             a.count = b.count;
-            launch_bucket(b, a, cs);
+            launch_bucket(h->fam, b, a, cs);
         }
     } else {
         // fork: every side stream waits for the caller's stream; buckets are dealt to the
@@ -557,7 +573,7 @@ extern "C" tron_err tron_batch_solve(tron_batch *h, const double *d_params, cons
             const Bucket &b = h->buckets[i];
             a.index = b.d_index;
             a.count = b.count;
-            launch_bucket(b, a, h->side[i % k]);
+            launch_bucket(h->fam, b, a, h->side[i % k]);
         }
         for (int i = 0; i < k && rc == TRON_OK; i++) {
             if (hipEventRecord(h->ev[1 + i], h->side[i]) != hipSuccess ||

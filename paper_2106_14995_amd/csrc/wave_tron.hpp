@@ -71,13 +71,131 @@ MT_INLINE double wave_max(double v)
     return max_nan(max_nan(bcast(v, 0), bcast(v, 16)), max_nan(bcast(v, 32), bcast(v, 48)));
 }
 
-// QP4 solved by one wave, R rows per lane (n <= 64 R).
-template <int R>
-struct WaveQP4 {
+// Objective families of the wave kernel. Each holds its own per-lane data and supplies
+//   load(s, p)     read the instance's parameters (after the solver has read l, u, x0);
+//   fg(s, v, g)    f(v) and its gradient on the lane's rows (0 on rows >= n);
+//   hess(s)        the Hessian at s.x: its diagonal into s.hd, its strict upper triangle
+//                  into the LDS array s.M when it depends on x.
+// QP4: f = x'Qx/2 + c'x + kappa sum x_i^4 (Q packed lower by rows, then c, then kappa); the
+// strict upper triangle of H is Q's and is written once at load.
+template <int R_>
+struct WaveFamQP4 {
+    static constexpr int R = R_;
+    double qd[R], c[R];  // Q's diagonal and c on the lane's rows
+    double kap;
+
+    template <class S>
+    MT_INLINE void load(S &s, const double *__restrict__ p)
+    {
+        const int n = s.n;
+        const double *cp = p + n * (n + 1) / 2;
+        kap = cp[n];
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const int i = s.row(r);
+            const bool in = i < n;
+            const int k = in ? i : 0;
+            qd[r] = in ? p[k * (k + 1) / 2 + k] : 0.0;
+            c[r] = in ? cp[k] : 0.0;
+        }
+        // strict upper part of Q (row i, column j > i = packed lower entry (j, i)); at each j
+        // the lanes i < j read consecutive addresses
+        for (int j = 1; j < n; j++) {
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = s.row(r);
+                if (i < j) s.M[i * s.ld + j] = p[j * (j + 1) / 2 + i];
+            }
+        }
+    }
+
+    template <class S>
+    MT_INLINE double fg(const S &s, const double (&v)[R], double (&gr)[R]) const
+    {
+        double y[R];
+        s.amul(v, qd, y);
+        double acc = 0.0;
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const double x2 = v[r] * v[r];
+            gr[r] = s.valid(r) ? fma(4.0 * kap * x2, v[r], y[r] + c[r]) : 0.0;
+            acc = fma(v[r], fma(0.5, y[r], c[r]), acc);
+            acc = fma(kap * x2, x2, acc);
+        }
+        return uni(wave_sum(acc));
+    }
+
+    template <class S>
+    MT_INLINE void hess(S &s) const
+    {
+        MT_UNROLL for (int r = 0; r < R; r++) s.hd[r] = fma(12.0 * kap * s.x[r], s.x[r], qd[r]);
+    }
+};
+
+// HS45M: f = 120 - prod_k x_k (no parameters). Products run over k in ascending order with
+// the excluded factors replaced by 1 (exact), so f and every gradient component carry the
+// rounding of the plain left-to-right product.
+template <int R_>
+struct WaveFamHS45M {
+    static constexpr int R = R_;
+
+    template <class S>
+    MT_INLINE void load(S &, const double *__restrict__) {}
+
+    template <class S>
+    MT_INLINE double fg(const S &s, const double (&v)[R], double (&gr)[R]) const
+    {
+        double pr = 1.0, q[R];
+        MT_UNROLL for (int r = 0; r < R; r++) q[r] = 1.0;
+        for (int k = 0; k < s.n; k++) {
+            const double xk = s.comp(v, k);
+            pr *= xk;
+            MT_UNROLL for (int r = 0; r < R; r++) q[r] *= s.row(r) == k ? 1.0 : xk;
+        }
+        MT_UNROLL for (int r = 0; r < R; r++) gr[r] = s.valid(r) ? -q[r] : 0.0;
+        return 120.0 - pr;
+    }
+
+    // H_ij = -prod_{k != i, j} x_k, H_ii = 0. Row i is the product of prefix and suffix
+    // products of y = x with y_i = 1: H_ij = -(prod_{k < j} y_k)(prod_{k > j} y_k). The prefix
+    // is stored in the strict upper row, then scaled by the suffix in a backward sweep.
+    template <class S>
+    MT_INLINE void hess(S &s) const
+    {
+        const int n = s.n, ld = s.ld;
+        double pre[R];
+        MT_UNROLL for (int r = 0; r < R; r++) pre[r] = 1.0;
+        for (int j = 0; j < n; j++) {
+            const double xj = s.comp(s.x, j);
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = s.row(r);
+                if (i < j) s.M[i * ld + j] = pre[r];
+                pre[r] *= i == j ? 1.0 : xj;
+            }
+        }
+        double suf[R];
+        MT_UNROLL for (int r = 0; r < R; r++) suf[r] = 1.0;
+        for (int j = n - 1; j >= 0; j--) {
+            const double xj = s.comp(s.x, j);
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = s.row(r);
+                if (i < j) s.M[i * ld + j] = -(s.M[i * ld + j] * suf[r]);
+                suf[r] *= i == j ? 1.0 : xj;
+            }
+        }
+        MT_UNROLL for (int r = 0; r < R; r++) s.hd[r] = 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+};
+
+// One trust-region Newton solve per wave for the family Fam, Fam::R rows per lane
+// (n <= 64 R).
+template <class Fam>
+struct WaveTron {
+    static constexpr int R = Fam::R;
+    Fam fam;
     int n, ld, lane;
     double *M;                 // LDS: L lower with diagonal, H strict upper, row stride ld
-    double qd[R], c[R], hd[R]; // Q diagonal, c, H diagonal (own rows)
-    double kap;
+    double hd[R];              // H diagonal (own rows)
     double lo[R], hi[R], x[R], g[R], xs[R], dinv[R];
     uint64_t lfm[R];           // free set of the last factored pass
     bool has_l;
@@ -131,49 +249,31 @@ struct WaveQP4 {
             y[r] = valid(r) ? (acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3]) : 0.0;
     }
 
+    // component k (< n) of a row-distributed vector, the same in every lane
+    MT_INLINE double comp(const double (&v)[R], int k) const
+    {
+        double t = v[0];
+        MT_UNROLL for (int r = 1; r < R; r++) t = (k >> 6) == r ? v[r] : t;
+        return bcast(t, k & 63);
+    }
+
     MT_INLINE void load(const double *__restrict__ p, const double *__restrict__ lop,
                         const double *__restrict__ hip_, const double *__restrict__ x0p)
     {
-        const double *cp = p + n * (n + 1) / 2;
-        kap = cp[n];
         MT_UNROLL for (int r = 0; r < R; r++) {
             const int i = row(r);
             const bool in = i < n;
             const int k = in ? i : 0;
-            qd[r] = in ? p[k * (k + 1) / 2 + k] : 0.0;
-            c[r] = in ? cp[k] : 0.0;
             lo[r] = in ? lop[k] : 0.0;
             hi[r] = in ? hip_[k] : 0.0;
             x[r] = in ? x0p[k] : 0.0;
         }
-        // strict upper part of Q (row i, column j > i = packed lower entry (j, i)); at each j
-        // the lanes i < j read consecutive addresses
-        for (int j = 1; j < n; j++) {
-            MT_UNROLL for (int r = 0; r < R; r++) {
-                const int i = row(r);
-                if (i < j) M[i * ld + j] = p[j * (j + 1) / 2 + i];
-            }
-        }
+        fam.load(*this, p);
     }
 
-    MT_INLINE double fg(const double (&v)[R], double (&gr)[R]) const
-    {
-        double y[R];
-        amul(v, qd, y);
-        double s = 0.0;
-        MT_UNROLL for (int r = 0; r < R; r++) {
-            const double x2 = v[r] * v[r];
-            gr[r] = valid(r) ? fma(4.0 * kap * x2, v[r], y[r] + c[r]) : 0.0;
-            s = fma(v[r], fma(0.5, y[r], c[r]), s);
-            s = fma(kap * x2, x2, s);
-        }
-        return uni(wave_sum(s));
-    }
+    MT_INLINE double fg(const double (&v)[R], double (&gr)[R]) const { return fam.fg(*this, v, gr); }
 
-    MT_INLINE void hess()
-    {
-        MT_UNROLL for (int r = 0; r < R; r++) hd[r] = fma(12.0 * kap * x[r], x[r], qd[r]);
-    }
+    MT_INLINE void hess() { fam.hess(*this); }
 
     MT_INLINE double pg_inf() const
     {
@@ -482,9 +582,7 @@ struct WaveQP4 {
         double t[R];
         MT_UNROLL for (int r = 0; r < R; r++) t[r] = 0.0;
         for (int k = 0; k < n; k++) {
-            double sk = s[0];
-            MT_UNROLL for (int r = 1; r < R; r++) sk = (k >> 6) == r ? s[r] : sk;
-            sk = bcast(sk, k & 63);
+            const double sk = comp(s, k);
             MT_UNROLL for (int r = 0; r < R; r++) {
                 const int i = row(r);
                 const bool in = i <= k;

@@ -24,7 +24,8 @@ Workload recipes:
     The nominal flows come from the complex power p + jq = y V_l conj(V_l - V_m) with
     y = g + jb, which is the same physics as the flow equations of the paper written in
     complex form.
-  * HS45M (the paper's modified hs45): f = 120 - prod x_i, 0 <= x_i <= i, x0_i = i/2.
+  * HS45M (the paper's modified hs45): f = 120 - prod x_i, 0 <= x_i <= i, x0_i = i/2 (the
+    paper's start), or x0_i ~ U[0, i] for the random-start variant.
   * Network for the ADMM: random recursive spanning tree plus distinct extra edges,
     generators on distinct buses, quadratic costs, loads scaled to the generation.
 """
@@ -214,6 +215,20 @@ def hs45m_batch(batch: int, n: int) -> Batch:
     i = np.arange(1, n + 1, dtype=np.float64)
     return Batch(HS45M, np.full(batch, n, dtype=np.int32), np.zeros(0), np.tile(np.zeros(n), batch),
                  np.tile(i, batch), np.tile(i / 2.0, batch))
+
+
+def hs45m_random_start(batch: int, n, config_id: int = 70) -> Batch:
+    """HS45M instances (0 <= x_i <= i) with x0_i ~ U[0, i]; n an int or one size per instance."""
+    ns = np.full(batch, n, dtype=np.int32) if np.isscalar(n) else np.asarray(n, dtype=np.int32)
+    los, his, x0s = [], [], []
+    for b in range(batch):
+        k = int(ns[b])
+        i = np.arange(1, k + 1, dtype=np.float64)
+        los.append(np.zeros(k))
+        his.append(i)
+        x0s.append(rng_for(config_id, b).uniform(0.0, 1.0, k) * i)
+    cat = lambda v: np.concatenate(v) if v else np.zeros(0)
+    return Batch(HS45M, ns, np.zeros(0), cat(los), cat(his), cat(x0s))
 
 
 # ------------------------------------------------------------------------------------

@@ -144,6 +144,30 @@ def test_hs45m_known_optimum(tron, n):
     assert np.allclose(g["f"], 120.0 - math.factorial(n), rtol=1e-14)
 
 
+@pytest.mark.parametrize("n", [9, 16, 32, 33, 64, 65, 100, 128])
+def test_hs45m_wave_known_optimum(tron, n):
+    """The wave kernel on the paper's hs45 variant: x* = (1, ..., n) exactly, and f computed
+    as 120 minus the left-to-right product, bitwise equal to the oracle's."""
+    import math
+    bt = W.hs45m_batch(70, n)
+    g = gpu_solve(tron, bt, gtol=1e-9)
+    ref = oracle_ref(bt, gtol=1e-9)
+    assert np.all(g["status"] == 0)
+    assert np.array_equal(g["x"].reshape(-1, n), np.tile(np.arange(1.0, n + 1), (70, 1)))
+    assert np.array_equal(g["f"], ref["f"])
+    assert np.allclose(g["f"], 120.0 - float(math.factorial(n)), rtol=1e-13)
+
+
+def test_hs45m_random_starts_mixed_sizes(tron):
+    """Random interior starts, n log-uniform in [1, 32]: lane and wave buckets in one batch,
+    every instance on the global minimiser (the upper corner), nonconvex parity bar."""
+    sizes = W.loguniform_sizes(1500, 1, 32, config_id=71)
+    bt = W.hs45m_random_start(1500, sizes, config_id=71)
+    g = gpu_solve(tron, bt)
+    check_parity(bt, g, oracle_ref(bt), convex=False)
+    assert np.array_equal(g["x"], bt.hi)
+
+
 def test_uneven_small_buckets(tron):
     sizes = W.loguniform_sizes(1111, 1, 8, config_id=30)
     bt = W.qp4_batch(1111, sizes, config_id=30)

@@ -102,7 +102,7 @@ def test_separable_quartic_closed_form(orc):
         assert np.abs(r["x"][k * n:(k + 1) * n] - xs).max() <= 1e-9
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 16, 32, 128])
 def test_hs45m_known_optimum(orc, n):
     """The paper's modified hs45: f = 120 - prod x_i with x_i <= i has x*_i = i (section 4.2
     footnote), so f* = 120 - n!."""
@@ -111,6 +111,18 @@ def test_hs45m_known_optimum(orc, n):
     assert np.all(r["status"] == 0)
     assert np.allclose(r["x"].reshape(4, n), np.arange(1, n + 1), atol=1e-12)
     assert np.allclose(r["f"], 120.0 - math.factorial(n), rtol=1e-14)
+
+
+def test_hs45m_random_starts(orc):
+    """Starts inside the box, 0 < x0_i < i. Accepted steps lower f, so the product stays
+    above its positive start and no x_i reaches 0; with every x_i > 0 each g_i is negative,
+    so the only stationary point left is the upper corner, x_i = i, hit exactly."""
+    sizes = W.loguniform_sizes(200, 1, 32, config_id=71)
+    bt = W.hs45m_random_start(200, sizes, config_id=71)
+    assert np.all(bt.x0 > 0.0) and np.all(bt.x0 < bt.hi)
+    r = orc.solve(bt, nthreads=4)
+    assert np.all(r["status"] == 0)
+    assert np.array_equal(r["x"], bt.hi)
 
 
 def test_br6_zero_residual(orc):
