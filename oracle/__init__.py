@@ -41,6 +41,11 @@ class Opts(C.Structure):
                 ("cg_rtol", C.c_double), ("delta0", C.c_double)]
 
 
+class AlOpts(C.Structure):
+    _fields_ = [("ctol", C.c_double), ("outer_max", C.c_int32), ("rho_growth", C.c_double),
+                ("decrease", C.c_double), ("rho_max", C.c_double)]
+
+
 class NetworkC(C.Structure):
     _fields_ = [("nbus", C.c_int32), ("nbranch", C.c_int32), ("ngen", C.c_int32),
                 ("ref_bus", C.c_int32), ("rho", C.c_double), ("base_mva", C.c_double),
@@ -81,6 +86,9 @@ def lib():
         L.or_projgrad_inf.argtypes = [C.c_int32, P, P, P, P]
         L.or_subspace_cg.restype = C.c_int32
         L.or_subspace_cg.argtypes = [C.c_int32, P, P, C.c_double, C.c_double, P, P, P, P]
+        L.or_al_batch.restype = C.c_int32
+        L.or_al_batch.argtypes = [C.c_int64, P, P, P, P, P, P, P, P, P, P, C.POINTER(Opts),
+                                  C.POINTER(AlOpts), C.c_int32]
         L.or_admm_state_size.restype = C.c_int64
         L.or_admm_state_size.argtypes = [C.POINTER(NetworkC)]
         L.or_admm_init.argtypes = [C.POINTER(NetworkC), P]
@@ -104,6 +112,25 @@ def _f64(a):
 
 def opts(gtol=1e-6, max_iter=500, cg_rtol=0.1, delta0=0.0, use_warm=0) -> Opts:
     return Opts(gtol, max_iter, use_warm, cg_rtol, delta0)
+
+
+def al_solve(batch, ctol=1e-6, outer_max=50, rho_growth=10.0, decrease=0.25, rho_max=1e6,
+             gtol=1e-6, max_iter=500, cg_rtol=0.1, delta0=0.0, nthreads=0):
+    """Augmented-Lagrangian loop over a BR8L batch (n = 8, 40 parameters per instance).
+    Returns a dict: x, f, status, iters, outer, viol, params (with the final multipliers and
+    penalties)."""
+    B = int(batch.n.shape[0])
+    assert batch.family == 3 and np.all(batch.n == 8)
+    params = _f64(batch.params).copy()
+    lo, hi, x0 = _f64(batch.lo), _f64(batch.hi), _f64(batch.x0)
+    x = np.zeros(8 * B)
+    f, viol = np.zeros(B), np.zeros(B)
+    status, iters, outer = (np.zeros(B, dtype=np.int32) for _ in range(3))
+    o = opts(gtol, max_iter, cg_rtol, delta0, 0)
+    a = AlOpts(ctol, outer_max, rho_growth, decrease, rho_max)
+    lib().or_al_batch(B, _p(params), _p(lo), _p(hi), _p(x0), _p(x), _p(f), _p(status), _p(iters),
+                      _p(outer), _p(viol), C.byref(o), C.byref(a), nthreads)
+    return dict(x=x, f=f, status=status, iters=iters, outer=outer, viol=viol, params=params)
 
 
 def param_size(family, n):

@@ -262,6 +262,7 @@ int64_t or_param_size(int32_t family, int32_t n)
 {
     if (family == OR_QP4) return (int64_t)n * (n + 1) / 2 + n + 1;
     if (family == OR_BR6) return 36;
+    if (family == OR_BR8L) return 40;
     return 0;
 }
 
@@ -462,6 +463,76 @@ static void br6_h(const double *p, const double *x, double *h, double *fl)
     }
 }
 
+/* BR8L: the branch subproblem with the line limits p_lm^2 + q_lm^2 <= smax^2 (eq. LineLimit)
+ * turned into equalities with slacks (the footnote of section 1 on inequalities):
+ *   h_lm(x) = p_lm^2 + q_lm^2 + sigma_lm - smax^2 = 0,   sigma_lm >= 0,   lm in {ij, ji},
+ * and added to the BR6 objective as the augmented-Lagrangian terms of section 1:
+ *   f = f_BR6(x_0..5) + sum_lm lambda_lm h_lm + rho_h/2 h_lm^2.
+ * x = (v_i, v_j, th_i, th_j, z_ij, z_ji, sigma_ij, sigma_ji); parameters: [0..35] as BR6,
+ * [36] smax^2, [37] lambda_ij, [38] lambda_ji, [39] rho_h.                               */
+static void br8l_limits(const double *p, const double *x, double hv[2])
+{
+    double y[8], fl = 0.0;
+    br6_couplings(p, x, 0, y, NULL, NULL, &fl);
+    for (int s = 0; s < 2; s++)
+        hv[s] = y[2 * s] * y[2 * s] + y[2 * s + 1] * y[2 * s + 1] + x[6 + s] - p[36];
+}
+
+static double br8l_f(const double *p, const double *x, double *fl)
+{
+    double f = br6_f(p, x, fl);
+    double hv[2];
+    br8l_limits(p, x, hv);
+    for (int s = 0; s < 2; s++) f += p[37 + s] * hv[s] + 0.5 * p[39] * hv[s] * hv[s];
+    *fl += 2.0 * 5.0 + 2.0 * 5.0;
+    return f;
+}
+
+static void br8l_g(const double *p, const double *x, double *g, double *fl)
+{
+    br6_g(p, x, g, fl);
+    double y[8], dy[8][4];
+    br6_couplings(p, x, 1, y, dy, NULL, fl);
+    for (int s = 0; s < 2; s++) {
+        int kp = 2 * s, kq = 2 * s + 1;
+        double hv = y[kp] * y[kp] + y[kq] * y[kq] + x[6 + s] - p[36];
+        double c = p[37 + s] + p[39] * hv;          /* d/dh of lambda h + rho/2 h^2 */
+        for (int i = 0; i < 4; i++) g[i] += c * (2.0 * y[kp] * dy[kp][i] + 2.0 * y[kq] * dy[kq][i]);
+        g[6 + s] = c;
+        *fl += 6.0 + 4.0 * 6.0;
+    }
+}
+
+static void br8l_h(const double *p, const double *x, double *h, double *fl)
+{
+    double h6[36];
+    br6_h(p, x, h6, fl);
+    for (int i = 0; i < 64; i++) h[i] = 0.0;
+    for (int i = 0; i < 6; i++)
+        for (int j = 0; j < 6; j++) h[i * 8 + j] = h6[i * 6 + j];
+    double y[8], dy[8][4], d2y[8][4][4];
+    br6_couplings(p, x, 2, y, dy, d2y, fl);
+    for (int s = 0; s < 2; s++) {
+        int kp = 2 * s, kq = 2 * s + 1, si = 6 + s;
+        double hv = y[kp] * y[kp] + y[kq] * y[kq] + x[si] - p[36];
+        double c = p[37 + s] + p[39] * hv;
+        /* gradient of h_lm over all 8 variables */
+        double u[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int i = 0; i < 4; i++) u[i] = 2.0 * y[kp] * dy[kp][i] + 2.0 * y[kq] * dy[kq][i];
+        u[si] = 1.0;
+        /* rho_h grad h grad h' + c Hess h, Hess h = 2 sum_{k in p,q} (dy dy' + y d2y) */
+        for (int i = 0; i < 8; i++)
+            for (int j = 0; j < 8; j++) h[i * 8 + j] += p[39] * u[i] * u[j];
+        for (int i = 0; i < 4; i++)
+            for (int j = 0; j < 4; j++) {
+                double hh = 2.0 * (dy[kp][i] * dy[kp][j] + y[kp] * d2y[kp][i][j] +
+                                   dy[kq][i] * dy[kq][j] + y[kq] * d2y[kq][i][j]);
+                h[i * 8 + j] += c * hh;
+            }
+        *fl += 6.0 + 4.0 * 6.0 + 64.0 * 3.0 + 16.0 * 11.0;
+    }
+}
+
 /* HS45M: f = 120 - prod x_i with 0 <= x_i <= i (footnote of section 4.2). */
 static double hs45_f(int n, const double *x, double *fl)
 {
@@ -497,6 +568,7 @@ static double fam_f(int fam, int n, const double *p, const double *x, double *fl
 {
     if (fam == OR_QP4) return qp4_f(n, p, x, fl);
     if (fam == OR_BR6) return br6_f(p, x, fl);
+    if (fam == OR_BR8L) return br8l_f(p, x, fl);
     return hs45_f(n, x, fl);
 }
 
@@ -504,6 +576,7 @@ static void fam_g(int fam, int n, const double *p, const double *x, double *g, d
 {
     if (fam == OR_QP4) qp4_g(n, p, x, g, fl);
     else if (fam == OR_BR6) br6_g(p, x, g, fl);
+    else if (fam == OR_BR8L) br8l_g(p, x, g, fl);
     else hs45_g(n, x, g, fl);
 }
 
@@ -511,6 +584,7 @@ static void fam_h(int fam, int n, const double *p, const double *x, double *h, d
 {
     if (fam == OR_QP4) qp4_h(n, p, x, h, fl);
     else if (fam == OR_BR6) br6_h(p, x, h, fl);
+    else if (fam == OR_BR8L) br8l_h(p, x, h, fl);
     else hs45_h(n, x, h, fl);
 }
 
@@ -1010,6 +1084,106 @@ int32_t or_tron_batch(int32_t family, int64_t batch, const int32_t *n_per, int32
     }
     free(poff);
     free(voff);
+    return nt;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Augmented-Lagrangian outer loop for the equality constraints of a BR8L instance        */
+/* (section 1: a sequence of bound-constrained minimisations of L_rho(x; lambda, rho) with */
+/* updates of (lambda, rho) between them). The paper leaves the update scheme to the      */
+/* literature it cites; reading S32 takes the first-order multiplier update with a penalty */
+/* increase when the violation did not shrink enough:                                    */
+/*   solve min_{l<=x<=u} L_rho(x; lambda) from the last x (warm radius after the first);  */
+/*   v = ||h(x)||_inf; stop when v <= ctol;                                               */
+/*   lambda <- lambda + rho h(x);                                                         */
+/*   rho <- min(growth * rho, rho_max) when v > decrease * v_previous.                    */
+/* The cap keeps the bound-constrained problems solvable to gtol: the gradient of the     */
+/* penalty term carries rounding noise of order rho * eps * |smax^2| * |grad h|.           */
+/* ------------------------------------------------------------------------------------ */
+static int al_one(const double *prm_in, const double *lo, const double *hi, const double *x0,
+                  double *prm_out, double *xout, double *fout, int32_t *iters, int32_t *outer,
+                  double *viol, const or_opts *o, const or_al_opts *al)
+{
+    double prm[40];
+    memcpy(prm, prm_in, sizeof(prm));
+    double xc[8], delta = 0.0, alphac = 0.0, f = NAN, v = INFINITY, vprev = INFINITY;
+    memcpy(xc, x0, sizeof(xc));
+    or_opts oi = *o;
+    int status = OR_AL_MAX_OUTER, total = 0, k = 0;
+    for (k = 0; k < al->outer_max; k++) {
+        double xn[8], st[OR_NSTAT];
+        int code = tron_one(OR_BR8L, 8, prm, lo, hi, xc, xn, &f, &delta, &alphac, &oi, st);
+        total += (int)st[1];
+        memcpy(xc, xn, sizeof(xc));
+        oi.use_warm = 1;
+        if (code != OR_CONVERGED) { status = code; k++; break; }
+        double hv[2];
+        br8l_limits(prm, xc, hv);
+        v = fabs(hv[0]) > fabs(hv[1]) ? fabs(hv[0]) : fabs(hv[1]);
+        if (!(v == v)) { status = OR_NONFINITE; k++; break; }
+        if (v <= al->ctol) { status = OR_CONVERGED; k++; break; }
+        prm[37] += prm[39] * hv[0];
+        prm[38] += prm[39] * hv[1];
+        if (v > al->decrease * vprev) {
+            double r = prm[39] * al->rho_growth;
+            prm[39] = r < al->rho_max ? r : al->rho_max;
+        }
+        vprev = v;
+    }
+    memcpy(prm_out, prm, sizeof(prm));
+    memcpy(xout, xc, sizeof(xc));
+    *fout = f;
+    *iters = total;
+    *outer = k;
+    *viol = v;
+    return status;
+}
+
+typedef struct {
+    int64_t batch;
+    double *params;
+    const double *lo, *hi, *x0;
+    double *x, *f, *viol;
+    int32_t *status, *iters, *outer;
+    const or_opts *opt;
+    const or_al_opts *al;
+    atomic_llong next;
+} al_job_t;
+
+static void *al_worker(void *arg)
+{
+    al_job_t *j = (al_job_t *)arg;
+    for (;;) {
+        long long b = atomic_fetch_add(&j->next, 1);
+        if (b >= j->batch) break;
+        double *pb = j->params + 40 * b;
+        j->status[b] = al_one(pb, j->lo + 8 * b, j->hi + 8 * b, j->x0 + 8 * b, pb, j->x + 8 * b,
+                              j->f + b, j->iters + b, j->outer + b, j->viol + b, j->opt, j->al);
+    }
+    return NULL;
+}
+
+int32_t or_al_batch(int64_t batch, double *params, const double *lo, const double *hi,
+                    const double *x0, double *x, double *f, int32_t *status, int32_t *iters,
+                    int32_t *outer, double *viol, const or_opts *opt, const or_al_opts *al,
+                    int32_t nthreads)
+{
+    if (batch <= 0) return 0;
+    al_job_t j;
+    j.batch = batch; j.params = params; j.lo = lo; j.hi = hi; j.x0 = x0; j.x = x; j.f = f;
+    j.viol = viol; j.status = status; j.iters = iters; j.outer = outer; j.opt = opt; j.al = al;
+    atomic_init(&j.next, 0);
+    int nt = nthreads;
+    if (nt <= 0) nt = (int)sysconf(_SC_NPROCESSORS_ONLN);
+    if (nt < 1) nt = 1;
+    if (nt > batch) nt = (int)batch;
+    if (nt == 1) al_worker(&j);
+    else {
+        pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * nt);
+        for (int t = 0; t < nt; t++) pthread_create(&th[t], NULL, al_worker, &j);
+        for (int t = 0; t < nt; t++) pthread_join(th[t], NULL);
+        free(th);
+    }
     return nt;
 }
 

@@ -23,9 +23,10 @@ extern "C" {
 #endif
 
 /* Problem families (same numbering as the GPU library's public enum; an interface). */
-enum { OR_QP4 = 0, OR_BR6 = 1, OR_HS45M = 2 };
-/* Per-instance outcomes. */
-enum { OR_CONVERGED = 0, OR_MAX_ITER = 1, OR_STALLED = 2, OR_NONFINITE = 3, OR_BAD_BOUNDS = 4 };
+enum { OR_QP4 = 0, OR_BR6 = 1, OR_HS45M = 2, OR_BR8L = 3 };
+/* Per-instance outcomes (OR_AL_MAX_OUTER: the multiplier loop hit its iteration cap). */
+enum { OR_CONVERGED = 0, OR_MAX_ITER = 1, OR_STALLED = 2, OR_NONFINITE = 3, OR_BAD_BOUNDS = 4,
+       OR_AL_MAX_OUTER = 5 };
 
 typedef struct {
     double gtol;     /* absolute bound on the infinity norm of the projected gradient      */
@@ -77,6 +78,23 @@ double or_projgrad_inf(int32_t n, const double *x, const double *lo, const doubl
  * 2 negative curvature, 3 trust boundary); w receives L^{-T} s_hat, *iters the count. */
 int32_t or_subspace_cg(int32_t m, const double *a, const double *r, double delta, double cg_rtol,
                        double *w, double *shat, int32_t *iters, double *shift_out);
+
+/* ---------------- augmented-Lagrangian loop (section 1) for BR8L instances ---------------- */
+typedef struct {
+    double ctol;       /* stop when ||h(x)||_inf <= ctol                                  */
+    int32_t outer_max; /* at most this many bound-constrained solves                       */
+    double rho_growth; /* penalty factor applied when the violation did not shrink enough  */
+    double decrease;   /* ... i.e. when ||h|| > decrease * previous ||h||                  */
+    double rho_max;    /* the penalty never grows beyond this                              */
+} or_al_opts;
+
+/* Per instance (n = 8, 40 parameters): solve, update lambda (params[37..38]) and rho_h
+ * (params[39]) in place, repeat. iters: total TRON iterations; outer: bound-constrained
+ * solves; viol: final ||h||_inf; f: the augmented Lagrangian at the last solve. */
+int32_t or_al_batch(int64_t batch, double *params, const double *lo, const double *hi,
+                    const double *x0, double *x, double *f, int32_t *status, int32_t *iters,
+                    int32_t *outer, double *viol, const or_opts *opt, const or_al_opts *al,
+                    int32_t nthreads);
 
 /* ---------------- component ADMM (section "Distributed control of ACOPF") ---------------- */
 typedef struct {

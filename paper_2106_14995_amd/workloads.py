@@ -24,6 +24,9 @@ Workload recipes:
     The nominal flows come from the complex power p + jq = y V_l conj(V_l - V_m) with
     y = g + jb, which is the same physics as the flow equations of the paper written in
     complex form.
+  * BR8L (BR6 with the line limits p^2 + q^2 <= smax^2 of both ends as equalities with
+    slacks, for the augmented-Lagrangian loop): smax = U[0.85, 1.3] x the larger nominal
+    |S|, lambda_h = 0, rho_h = 10, slacks in [0, smax^2] starting feasible.
   * HS45M (the paper's modified hs45): f = 120 - prod x_i, 0 <= x_i <= i, x0_i = i/2 (the
     paper's start), or x0_i ~ U[0, i] for the random-start variant.
   * Network for the ADMM: random recursive spanning tree plus distinct extra edges,
@@ -36,8 +39,8 @@ import math
 import numpy as np
 
 ENTROPY = 210614995
-QP4, BR6, HS45M = 0, 1, 2
-FAMILY_NAMES = {QP4: "qp4", BR6: "br6", HS45M: "hs45m"}
+QP4, BR6, HS45M, BR8L = 0, 1, 2, 3
+FAMILY_NAMES = {QP4: "qp4", BR6: "br6", HS45M: "hs45m", BR8L: "br8l"}
 
 
 def rng_for(config_id: int, instance_id: int) -> np.random.Generator:
@@ -50,6 +53,8 @@ def param_size(family: int, n: int) -> int:
         return n * (n + 1) // 2 + n + 1
     if family == BR6:
         return 36
+    if family == BR8L:
+        return 40
     return 0
 
 
@@ -180,6 +185,32 @@ def br6_batch(batch: int, config_id: int = 1, first: int = 0) -> Batch:
     x0 = np.concatenate(xs) if xs else np.zeros(0)
     return Batch(BR6, np.full(batch, 6, dtype=np.int32), params, np.tile(BR6_LO, batch),
                  np.tile(BR6_HI, batch), x0)
+
+
+def br8l_instance(rng: np.random.Generator, rho_h: float = 10.0):
+    """A BR6 instance plus apparent-power limits on both ends: smax = U[0.85, 1.3] times the
+    larger nominal |S| (binding on about half the instances), lambda_h = 0, rho_h given;
+    slacks start at the value that makes the limit equalities hold at the start."""
+    params, lo, hi, x0 = br6_instance(rng)
+    g, b = params[0], params[1]
+    pq = complex_flows(g, b, x0[0], x0[1], x0[2], x0[3])
+    s2 = np.array([pq[0] ** 2 + pq[1] ** 2, pq[2] ** 2 + pq[3] ** 2])
+    smax2 = (rng.uniform(0.85, 1.3) ** 2) * float(s2.max())
+    params = np.concatenate([params, [smax2, 0.0, 0.0, rho_h]])
+    lo = np.concatenate([lo, [0.0, 0.0]])
+    hi = np.concatenate([hi, [smax2, smax2]])
+    x0 = np.concatenate([x0, np.clip(smax2 - s2, 0.0, smax2)])
+    return params, lo, hi, x0
+
+
+def br8l_batch(batch: int, config_id: int = 5, first: int = 0, rho_h: float = 10.0) -> Batch:
+    """Branch subproblems with line limits (family BR8L, n = 8, 40 parameters)."""
+    ps, ls, hs, xs = [], [], [], []
+    for k in range(batch):
+        p, lo, hi, x = br8l_instance(rng_for(config_id, first + k), rho_h)
+        ps.append(p); ls.append(lo); hs.append(hi); xs.append(x)
+    cat = lambda v: np.concatenate(v) if v else np.zeros(0)
+    return Batch(BR8L, np.full(batch, 8, dtype=np.int32), cat(ps), cat(ls), cat(hs), cat(xs))
 
 
 def br6_zero_residual(batch: int, config_id: int = 91) -> Batch:
