@@ -50,7 +50,8 @@ enum {
     TRON_MAX_ITER = 1,    /* max_iter trust-region iterations taken                       */
     TRON_STALLED = 2,     /* no model decrease possible / reductions at rounding level    */
     TRON_NONFINITE = 3,   /* f or grad f not finite at an accepted point                  */
-    TRON_BAD_BOUNDS = 4   /* some l_i > u_i (or a NaN bound); x is left at x0             */
+    TRON_BAD_BOUNDS = 4,  /* some l_i > u_i (or a NaN bound); x is left at x0             */
+    TRON_AL_MAX_OUTER = 5 /* tron_al_solve: outer_max solves without ||h||_inf <= ctol    */
 };
 
 /* Problem families. Parameter block sizes (doubles per instance):
@@ -63,8 +64,19 @@ enum {
  *          penalties of the eight couplings, [34..35] penalties of the two z couplings;
  *          flows per eqs. pij..qji with w = v^2, wR = v_i v_j cos(th_i - th_j),
  *          wI = v_i v_j sin(th_i - th_j).
- *   HS45M: 0 -- f = 120 - prod x_i (the variant of hs45 in section 4.2). 1 <= n <= 128. */
-typedef enum { TRON_FAMILY_QP4 = 0, TRON_FAMILY_BR6 = 1, TRON_FAMILY_HS45M = 2 } tron_family;
+ *   HS45M: 0 -- f = 120 - prod x_i (the variant of hs45 in section 4.2). 1 <= n <= 128.
+ *   BR8L:  40, n = 8 -- BR6 with the line limits of eq. LineLimit on both ends written as
+ *          equalities with slacks (the footnote on inequalities in section 1),
+ *          h_lm = p_lm^2 + q_lm^2 + sigma_lm - smax^2, added as the augmented-Lagrangian
+ *          terms lambda_lm h_lm + rho_h/2 h_lm^2 of section 1. x = (v_i, v_j, th_i, th_j,
+ *          z_ij, z_ji, sigma_ij, sigma_ji); [0..35] as BR6, [36] smax^2, [37] lambda_ij,
+ *          [38] lambda_ji, [39] rho_h. */
+typedef enum {
+    TRON_FAMILY_QP4 = 0,
+    TRON_FAMILY_BR6 = 1,
+    TRON_FAMILY_HS45M = 2,
+    TRON_FAMILY_BR8L = 3
+} tron_family;
 
 typedef struct {
     double gtol;       /* absolute tolerance on ||grad_[l,u] f||_inf (default 1e-6)          */
@@ -141,6 +153,37 @@ tron_err tron_autotune(tron_family family, int64_t batch, const int32_t *n_host,
 tron_err tron_batch_solve(tron_batch *h, const double *d_params, const double *d_lo,
                           const double *d_hi, const double *d_x0, double *d_x, double *d_f,
                           int32_t *d_status, int32_t *d_iters, void *stream);
+
+/* Augmented-Lagrangian loop (section 1: general constraints h(x) = 0 through a sequence of
+ * bound-constrained minimisations of L_rho(x; lambda, rho) with (lambda, rho) updated in
+ * between). The paper leaves the update to the literature it cites; this one is the
+ * first-order multiplier step lambda <- lambda + rho h(x) with
+ * rho <- min(rho_growth * rho, rho_max) whenever ||h||_inf > decrease * its previous value,
+ * stopping when ||h||_inf <= ctol. */
+typedef struct {
+    double ctol;        /* stop when ||h(x)||_inf <= ctol (default 1e-6)                      */
+    int32_t outer_max;  /* bound-constrained solves per instance at most (default 50)         */
+    double rho_growth;  /* >= 1 (default 10)                                                  */
+    double decrease;    /* >= 0 (default 0.25)                                                */
+    double rho_max;     /* > 0 (default 1e6)                                                  */
+} tron_al_options;
+
+void tron_default_al_options(tron_al_options *o);
+
+/* Run the loop on every instance of a BR8L handle, one GPU lane per instance, entirely on
+ * the device. Each solve uses the handle's tron_options; the first starts from d_x0 (and
+ * from the resident radius when TRON_FLAG_WARM is set), later ones from the previous x and
+ * radius. d_params (batch x 40 doubles) is read and updated in place: on return [37..38]
+ * hold the last multipliers and [39] the last penalty, ready for a warm restart. Outputs:
+ * d_x (batch x 8), d_f (L_rho at the last solve), d_status (TRON_CONVERGED when the last
+ * solve converged and ||h||_inf <= ctol, TRON_AL_MAX_OUTER, or the failing solve's status),
+ * d_iters (TRON iterations over all solves), d_outer (solves taken) and d_viol (the last
+ * ||h||_inf). Asynchronous on `stream`.
+ * Errors: INVALID (null pointers, bad options), UNSUPPORTED (not a BR8L handle), DEVICE. */
+tron_err tron_al_solve(tron_batch *h, const tron_al_options *opt, double *d_params,
+                       const double *d_lo, const double *d_hi, const double *d_x0, double *d_x,
+                       double *d_f, int32_t *d_status, int32_t *d_iters, int32_t *d_outer,
+                       double *d_viol, void *stream);
 
 /* Copy the resident per-instance state out of / into the handle: d_state holds 2*batch
  * doubles, the radii then the Cauchy step lengths. Used for checkpoint and resume. */

@@ -45,7 +45,7 @@ constexpr int kShiftTries = 64;
 constexpr double kStallRel = 1e-15;
 constexpr double kAredSwitch = 1e-10;
 
-enum : int32_t { kConverged = 0, kMaxIter = 1, kStalled = 2, kNonfinite = 3, kBadBounds = 4 };
+enum : int32_t { kConverged = 0, kMaxIter = 1, kStalled = 2, kNonfinite = 3, kBadBounds = 4, kAlMaxOuter = 5 };
 enum : int { kCgConv = 0, kCgMaxit = 1, kCgNeg = 2, kCgBnd = 3 };
 
 // packed lower-triangular index, row by row
@@ -283,6 +283,139 @@ struct BR6 {
         h[tri(5, 5)] = rz1;
     }
     MT_INLINE double H(int i, int j) const { return h[tri(i, j)]; }
+};
+
+// BR8L: BR6 plus the line limits of both ends as equalities with slacks,
+//   h_lm = p_lm^2 + q_lm^2 + sigma_lm - smax^2,  lm in {ij, ji},
+// entering through the augmented-Lagrangian terms lambda_lm h_lm + rho_h/2 h_lm^2 (section 1
+// and its footnote on inequalities). x = (v_i, v_j, th_i, th_j, z_ij, z_ji, sigma_ij,
+// sigma_ji); parameters [0..35] as BR6, [36] smax^2, [37..38] lambda, [39] rho_h.
+// The limit terms are differentiated in (v_i, v_j, D, sigma) like BR6's flows and mapped
+// to (th_i, th_j) the same way.
+struct BR8L {
+    static constexpr int N = 8;
+    static constexpr int T = 36;
+    static constexpr double pad = 0.0;
+    BR6 b6;                // the BR6 part; its Hessian block also receives the limit terms
+    double smax2, lam[2], rhoh;
+    double hs[2][4];       // slack rows of the Hessian against (v_i, v_j, th_i, th_j)
+
+    MT_INLINE void load(const double *__restrict__ p, int n)
+    {
+        b6.load(p, n);
+        smax2 = p[36];
+        lam[0] = p[37];
+        lam[1] = p[38];
+        rhoh = p[39];
+    }
+
+    // flow k (p_ij, q_ij, p_ji, q_ji) at (vi, vj) with the cached cos/sin of D: value,
+    // gradient in (vi, vj, D) and the six distinct second derivatives
+    // (vi vi, vj vj, vi vj, vi D, vj D, D D)
+    MT_INLINE void flow(int k, double vi, double vj, double &y, double (&d)[3], double (&d2)[6]) const
+    {
+        const double al = b6.fal(k), be = b6.fbe(k), a = b6.fa(k), V = vi * vj;
+        const double phi = fma(al, b6.cth, be * b6.sth);
+        const double psi = fma(-al, b6.sth, be * b6.cth);
+        const double a2 = 2.0 * a;
+        const bool own_i = k < 2;
+        y = own_i ? fma(a * vi, vi, V * phi) : fma(a * vj, vj, V * phi);
+        d[0] = own_i ? fma(vj, phi, a2 * vi) : vj * phi;
+        d[1] = own_i ? vi * phi : fma(vi, phi, a2 * vj);
+        d[2] = V * psi;
+        d2[0] = own_i ? a2 : 0.0;
+        d2[1] = own_i ? 0.0 : a2;
+        d2[2] = phi;
+        d2[3] = vj * psi;
+        d2[4] = vi * psi;
+        d2[5] = -V * phi;
+    }
+
+    // the two limit residuals at x (sets the cached angle of b6 to x's)
+    MT_INLINE void limits(const double (&x)[8], double (&hv)[2])
+    {
+        sincos(x[2] - x[3], &b6.sth, &b6.cth);
+        MT_UNROLL for (int l = 0; l < 2; l++) {
+            double yp, yq, d[3], d2[6];
+            flow(2 * l, x[0], x[1], yp, d, d2);
+            flow(2 * l + 1, x[0], x[1], yq, d, d2);
+            hv[l] = fma(yp, yp, fma(yq, yq, x[6 + l] - smax2));
+        }
+    }
+
+    MT_INLINE double fg(const double (&x)[8], double (&g)[8])
+    {
+        double x6[6], g6[6];
+        MT_UNROLL for (int i = 0; i < 6; i++) x6[i] = x[i];
+        double f = b6.fg(x6, g6);  // caches cos/sin of th_i - th_j at x
+        MT_UNROLL for (int i = 0; i < 6; i++) g[i] = g6[i];
+        MT_UNROLL for (int l = 0; l < 2; l++) {
+            double yp, yq, dp[3], dq[3], d2[6];
+            flow(2 * l, x[0], x[1], yp, dp, d2);
+            flow(2 * l + 1, x[0], x[1], yq, dq, d2);
+            const double hv = fma(yp, yp, fma(yq, yq, x[6 + l] - smax2));
+            const double c = fma(rhoh, hv, lam[l]);
+            f = fma(fma(0.5 * rhoh, hv, lam[l]), hv, f);
+            const double c2 = 2.0 * c;
+            const double uD = c2 * fma(yp, dp[2], yq * dq[2]);
+            g[0] = fma(c2, fma(yp, dp[0], yq * dq[0]), g[0]);
+            g[1] = fma(c2, fma(yp, dp[1], yq * dq[1]), g[1]);
+            g[2] += uD;
+            g[3] -= uD;
+            g[6 + l] = c;
+        }
+        return f;
+    }
+
+    MT_INLINE void hess(const double (&x)[8])
+    {
+        double x6[6];
+        MT_UNROLL for (int i = 0; i < 6; i++) x6[i] = x[i];
+        b6.hess(x6);  // uses the angle cached by the last fg, which was at x
+        MT_UNROLL for (int l = 0; l < 2; l++) {
+            double yp, yq, dp[3], dq[3], d2p[6], d2q[6];
+            flow(2 * l, x[0], x[1], yp, dp, d2p);
+            flow(2 * l + 1, x[0], x[1], yq, dq, d2q);
+            const double hv = fma(yp, yp, fma(yq, yq, x[6 + l] - smax2));
+            const double c2 = 2.0 * fma(rhoh, hv, lam[l]);
+            // grad h in (vi, vj, D); sigma_l enters with 1
+            double u[3];
+            MT_UNROLL for (int a = 0; a < 3; a++) u[a] = 2.0 * fma(yp, dp[a], yq * dq[a]);
+            // M = rho u u' + 2c (dp dp' + yp d2p + dq dq' + yq d2q) on (vi, vj, D)
+            const int ia[6] = {0, 1, 0, 0, 1, 2}, ib[6] = {0, 1, 1, 2, 2, 2};
+            double m[6];
+            MT_UNROLL for (int e = 0; e < 6; e++) {
+                const int a = ia[e], bb = ib[e];
+                const double cur = fma(dp[a], dp[bb], fma(yp, d2p[e], fma(dq[a], dq[bb], yq * d2q[e])));
+                m[e] = fma(rhoh * u[a], u[bb], c2 * cur);
+            }
+            // (vi, vj, D) -> (vi, vj, th_i, th_j), added to the BR6 block in place
+            double *h6 = b6.h;
+            h6[tri(0, 0)] += m[0];
+            h6[tri(1, 1)] += m[1];
+            h6[tri(1, 0)] += m[2];
+            h6[tri(2, 0)] += m[3];
+            h6[tri(3, 0)] -= m[3];
+            h6[tri(2, 1)] += m[4];
+            h6[tri(3, 1)] -= m[4];
+            h6[tri(2, 2)] += m[5];
+            h6[tri(3, 3)] += m[5];
+            h6[tri(3, 2)] -= m[5];
+            // the slack row: rho (u_vi, u_vj, u_D, -u_D) against (v_i, v_j, th_i, th_j)
+            hs[l][0] = rhoh * u[0];
+            hs[l][1] = rhoh * u[1];
+            hs[l][2] = rhoh * u[2];
+            hs[l][3] = -rhoh * u[2];
+        }
+    }
+    // i, j are compile-time after unrolling, so the selection costs nothing
+    MT_INLINE double H(int i, int j) const
+    {
+        if (i < 6 && j < 6) return b6.h[tri(i, j)];
+        const int r = i > j ? i : j, c = i > j ? j : i;  // r is a slack row (6 or 7)
+        if (c == r) return rhoh;
+        return c < 4 ? hs[r - 6][c] : 0.0;
+    }
 };
 
 // ------------------------------------------------------------------------------------

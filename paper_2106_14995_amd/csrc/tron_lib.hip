@@ -54,6 +54,7 @@ extern "C" int64_t tron_param_size(tron_family fam, int32_t n)
     if (fam == TRON_FAMILY_QP4 && n >= 1 && n <= 128) return (int64_t)n * (n + 1) / 2 + n + 1;
     if (fam == TRON_FAMILY_BR6 && n == 6) return 36;
     if (fam == TRON_FAMILY_HS45M && n >= 1 && n <= 128) return 0;
+    if (fam == TRON_FAMILY_BR8L && n == 8) return 40;
     return -1;
 }
 
@@ -112,6 +113,7 @@ static lane_launch_fn lane_launcher(tron_family fam, int N)
 {
     using namespace mt;
     if (fam == TRON_FAMILY_BR6) return N == 6 ? launch_lane<BR6, 6> : nullptr;
+    if (fam == TRON_FAMILY_BR8L) return N == 8 ? launch_lane<BR8L, 8> : nullptr;
     if (fam == TRON_FAMILY_QP4) {
         switch (N) {
         case 1: return launch_lane<QP4<1>, 1>;
@@ -140,6 +142,70 @@ static lane_launch_fn lane_launcher(tron_family fam, int N)
 }
 
 void mt_launch_br6(const LaneArgs &a, hipStream_t st) { launch_lane<mt::BR6, 6>(a, st); }
+
+// ------------------------------------------------------------------------------------
+// augmented-Lagrangian loop for BR8L (section 1): each lane repeats the bound-constrained
+// solve of its own instance and updates its multipliers and penalty in registers, so
+// instances finish their outer loops independently and nothing returns to the host
+// ------------------------------------------------------------------------------------
+struct AlArgs {
+    double *params;   // in/out: multipliers [37..38] and penalty [39] are updated
+    int32_t *outer;
+    double *viol;
+    double ctol, rho_growth, decrease, rho_max;
+    int32_t outer_max;
+};
+
+__global__ __launch_bounds__(kLaneBlock) void al_kernel(LaneArgs a, AlArgs al)
+{
+    constexpr int N = 8;
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.count) return;
+    mt::LaneTron<mt::BR8L, N> s;
+    double *prm = al.params + 40 * b;
+    s.fam.load(prm, N);
+    const double *lo = a.lo + N * b, *hi = a.hi + N * b, *x0 = a.x0 + N * b;
+    MT_UNROLL for (int i = 0; i < N; i++) {
+        s.lo[i] = lo[i];
+        s.hi[i] = hi[i];
+        s.x[i] = x0[i];
+    }
+    mt::Options o = a.opt;
+    double din = o.warm ? a.state[b] : 0.0;
+    double ain = o.warm ? a.state[a.batch + b] : 0.0;
+    int32_t status = mt::kAlMaxOuter, total = 0, k = 0;
+    double v = __builtin_inf(), vprev = __builtin_inf();
+    while (k < al.outer_max) {
+        const int32_t st = s.solve(o, din, ain);
+        total += s.iters;
+        k++;
+        o.warm = 1;
+        din = s.delta;
+        ain = s.alphac;
+        if (st != mt::kConverged) { status = st; break; }
+        double hv[2];
+        s.fam.limits(s.x, hv);
+        v = fabs(hv[0]) > fabs(hv[1]) ? fabs(hv[0]) : fabs(hv[1]);
+        if (!(v == v)) { status = mt::kNonfinite; break; }
+        if (v <= al.ctol) { status = mt::kConverged; break; }
+        s.fam.lam[0] += s.fam.rhoh * hv[0];
+        s.fam.lam[1] += s.fam.rhoh * hv[1];
+        if (v > al.decrease * vprev) s.fam.rhoh = mt::dmin(s.fam.rhoh * al.rho_growth, al.rho_max);
+        vprev = v;
+    }
+    double *xo = a.x + N * b;
+    MT_UNROLL for (int i = 0; i < N; i++) xo[i] = s.x[i];
+    a.f[b] = s.f;
+    a.status[b] = status;
+    a.iters[b] = total;
+    a.state[b] = s.delta;
+    a.state[a.batch + b] = s.alphac;
+    al.outer[b] = k;
+    al.viol[b] = v;
+    prm[37] = s.fam.lam[0];
+    prm[38] = s.fam.lam[1];
+    prm[39] = s.fam.rhoh;
+}
 
 // ------------------------------------------------------------------------------------
 // wavefront-per-instance kernels (8 < n <= 128; QP4 and HS45M); one 64-lane workgroup per
@@ -429,7 +495,8 @@ extern "C" tron_err tron_batch_create_ex(tron_batch **out, tron_family fam, int6
     if (!out) return mt_fail(TRON_ERR_INVALID, "out is null");
     *out = nullptr;
     if (batch < 0 || batch > (int64_t)INT32_MAX) return mt_fail(TRON_ERR_INVALID, "batch out of range");
-    if (fam != TRON_FAMILY_QP4 && fam != TRON_FAMILY_BR6 && fam != TRON_FAMILY_HS45M)
+    if (fam != TRON_FAMILY_QP4 && fam != TRON_FAMILY_BR6 && fam != TRON_FAMILY_HS45M &&
+        fam != TRON_FAMILY_BR8L)
         return mt_fail(TRON_ERR_INVALID, "unknown family");
     tron_options o;
     tron_default_options(&o);
@@ -599,6 +666,53 @@ extern "C" tron_err tron_batch_solve(tron_batch *h, const double *d_params, cons
         return TRON_OK;
     }
     if (rc != TRON_OK) return rc;
+    HIP_TRY(hipGetLastError());
+    return TRON_OK;
+}
+
+extern "C" void tron_default_al_options(tron_al_options *o)
+{
+    if (!o) return;
+    o->ctol = 1e-6;
+    o->outer_max = 50;
+    o->rho_growth = 10.0;
+    o->decrease = 0.25;
+    o->rho_max = 1e6;
+}
+
+extern "C" tron_err tron_al_solve(tron_batch *h, const tron_al_options *opt, double *d_params,
+                                  const double *d_lo, const double *d_hi, const double *d_x0,
+                                  double *d_x, double *d_f, int32_t *d_status, int32_t *d_iters,
+                                  int32_t *d_outer, double *d_viol, void *stream)
+{
+    if (!h) return mt_fail(TRON_ERR_INVALID, "handle is null");
+    if (h->fam != TRON_FAMILY_BR8L) return mt_fail(TRON_ERR_UNSUPPORTED, "the multiplier loop needs a BR8L batch");
+    tron_al_options o;
+    tron_default_al_options(&o);
+    if (opt) o = *opt;
+    if (!(o.ctol >= 0.0) || o.outer_max < 1 || !(o.rho_growth >= 1.0) || !(o.decrease >= 0.0) ||
+        !(o.rho_max > 0.0))
+        return mt_fail(TRON_ERR_INVALID, "invalid multiplier-loop options");
+    if (h->batch == 0) return TRON_OK;
+    if (!d_params || !d_lo || !d_hi || !d_x0 || !d_x || !d_f || !d_status || !d_iters || !d_outer || !d_viol)
+        return mt_fail(TRON_ERR_INVALID, "null device pointer");
+    LaneArgs a{};
+    a.lo = d_lo;
+    a.hi = d_hi;
+    a.x0 = d_x0;
+    a.x = d_x;
+    a.f = d_f;
+    a.status = d_status;
+    a.iters = d_iters;
+    a.state = h->d_state;
+    a.count = h->batch;
+    a.batch = h->batch;
+    a.n_uniform = 8;
+    a.psize = 40;
+    a.opt = dev_options(h->opt);
+    AlArgs al{d_params, d_outer, d_viol, o.ctol, o.rho_growth, o.decrease, o.rho_max, o.outer_max};
+    const unsigned grid = (unsigned)((h->batch + kLaneBlock - 1) / kLaneBlock);
+    hipLaunchKernelGGL(al_kernel, dim3(grid), dim3(kLaneBlock), 0, (hipStream_t)stream, a, al);
     HIP_TRY(hipGetLastError());
     return TRON_OK;
 }

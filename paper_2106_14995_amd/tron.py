@@ -13,8 +13,8 @@ import numpy as np
 
 from . import build as _build
 
-QP4, BR6, HS45M = 0, 1, 2
-CONVERGED, MAX_ITER, STALLED, NONFINITE, BAD_BOUNDS = 0, 1, 2, 3, 4
+QP4, BR6, HS45M, BR8L = 0, 1, 2, 3
+CONVERGED, MAX_ITER, STALLED, NONFINITE, BAD_BOUNDS, AL_MAX_OUTER = 0, 1, 2, 3, 4, 5
 FLAG_WARM = 1
 FLAG_GRAPH = 2
 ERRORS = {1: "invalid argument", 2: "out of memory", 3: "device error", 4: "unsupported",
@@ -30,6 +30,11 @@ class TronError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [("gtol", C.c_double), ("max_iter", C.c_int32), ("flags", C.c_uint32),
                 ("cg_rtol", C.c_double), ("delta0", C.c_double)]
+
+
+class AlOptions(C.Structure):
+    _fields_ = [("ctol", C.c_double), ("outer_max", C.c_int32), ("rho_growth", C.c_double),
+                ("decrease", C.c_double), ("rho_max", C.c_double)]
 
 
 class PlanSpec(C.Structure):
@@ -63,7 +68,8 @@ EXPORTS = ("tron_default_options", "tron_last_error", "tron_param_size", "tron_b
            "admm_destroy", "tron_server_default_config", "tron_server_create", "tron_server_submit",
            "tron_server_poll", "tron_server_wait", "tron_server_result", "tron_server_close_session",
            "tron_server_stats", "tron_server_destroy", "tron_batch_set_timestamps", "tron_clock_rate_hz",
-           "tron_default_plan_spec", "tron_batch_create_ex", "tron_autotune")
+           "tron_default_plan_spec", "tron_batch_create_ex", "tron_autotune",
+           "tron_default_al_options", "tron_al_solve")
 
 
 def lib_path() -> str:
@@ -94,6 +100,8 @@ def lib():
                                            C.POINTER(PlanSpec), P]
         L.tron_autotune.argtypes = [I32, I64, P, P, P, P, P, P, P, P, P, I32, C.c_char_p,
                                     C.POINTER(PlanSpec), C.POINTER(C.c_double), P]
+        L.tron_default_al_options.argtypes = [C.POINTER(AlOptions)]
+        L.tron_al_solve.argtypes = [P, C.POINTER(AlOptions)] + [P] * 11
         L.tron_clock_rate_hz.restype = I64
         L.tron_batch_set_timestamps.argtypes = [P, P]
         L.tron_server_default_config.argtypes = [C.POINTER(ServerConfig)]
@@ -198,6 +206,29 @@ class Batch:
                 _dev(iters, i32, self.batch, "iters")]
         _check(lib().tron_batch_solve(self._h, *args, _stream_ptr(stream)))
         return x, f, status, iters
+
+    def al_solve(self, params, lo, hi, x0, ctol=1e-6, outer_max=50, rho_growth=10.0,
+                 decrease=0.25, rho_max=1e6, x=None, stream=None):
+        """Multiplier loop on a BR8L batch; `params` (device, batch x 40) is updated in place.
+        Returns x, f, status, iters, outer, viol (device tensors)."""
+        import torch
+        dev = lo.device
+        f64, i32 = torch.float64, torch.int32
+        if x is None:
+            x = torch.empty(self.nsum, dtype=f64, device=dev)
+        f = torch.empty(self.batch, dtype=f64, device=dev)
+        viol = torch.empty(self.batch, dtype=f64, device=dev)
+        status, iters, outer = (torch.empty(self.batch, dtype=i32, device=dev) for _ in range(3))
+        o = AlOptions()
+        lib().tron_default_al_options(C.byref(o))
+        o.ctol, o.outer_max, o.rho_growth, o.decrease, o.rho_max = ctol, outer_max, rho_growth, decrease, rho_max
+        _check(lib().tron_al_solve(self._h, C.byref(o), _dev(params, f64, self.psum, "params"),
+                                   _dev(lo, f64, self.nsum, "lo"), _dev(hi, f64, self.nsum, "hi"),
+                                   _dev(x0, f64, self.nsum, "x0"), _dev(x, f64, self.nsum, "x"),
+                                   _dev(f, f64, self.batch, "f"), _dev(status, i32, self.batch, "status"),
+                                   _dev(iters, i32, self.batch, "iters"), _dev(outer, i32, self.batch, "outer"),
+                                   _dev(viol, f64, self.batch, "viol"), _stream_ptr(stream)))
+        return x, f, status, iters, outer, viol
 
     def get_state(self, out=None, stream=None):
         import torch

@@ -37,8 +37,21 @@ def test_host_helpers():
     assert tron.param_size(tron.BR6, 6) == 36
     assert tron.param_size(tron.BR6, 5) == -1
     assert tron.param_size(tron.HS45M, 4) == 0
+    assert tron.param_size(tron.HS45M, 128) == 0
+    assert tron.param_size(tron.BR8L, 8) == 40
+    assert tron.param_size(tron.BR8L, 6) == -1
     o = tron.options()
     assert o.gtol == 1e-6 and o.max_iter == 500 and o.cg_rtol == 0.1 and o.flags == 0
+    a = tron.AlOptions()
+    tron.lib().tron_default_al_options(C.byref(a))
+    assert (a.ctol, a.outer_max, a.rho_growth, a.decrease, a.rho_max) == (1e-6, 50, 10.0, 0.25, 1e6)
+
+
+def test_al_solve_rejects_bad_arguments_before_touching_the_device():
+    from paper_2106_14995_amd import tron
+    L = tron.lib()
+    null = [None] * 10
+    assert L.tron_al_solve(None, None, *null, None) == 1
 
 
 def test_create_rejects_bad_arguments_before_touching_the_device():
