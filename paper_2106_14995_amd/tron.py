@@ -69,7 +69,9 @@ EXPORTS = ("tron_default_options", "tron_last_error", "tron_param_size", "tron_b
            "tron_server_poll", "tron_server_wait", "tron_server_result", "tron_server_close_session",
            "tron_server_stats", "tron_server_destroy", "tron_batch_set_timestamps", "tron_clock_rate_hz",
            "tron_default_plan_spec", "tron_batch_create_ex", "tron_autotune",
-           "tron_default_al_options", "tron_al_solve")
+           "tron_default_al_options", "tron_al_solve", "tron_design_chol", "tron_design_trsv")
+CHOL_LEFT_LDS, CHOL_RIGHT_LDS, CHOL_LEFT_GLOBAL = 0, 1, 2
+TRSV_IMPLICIT, TRSV_PADDED, TRSV_EXPLICIT, TRSV_GLOBAL = 0, 1, 2, 3
 
 
 def lib_path() -> str:
@@ -102,6 +104,8 @@ def lib():
                                     C.POINTER(PlanSpec), C.POINTER(C.c_double), P]
         L.tron_default_al_options.argtypes = [C.POINTER(AlOptions)]
         L.tron_al_solve.argtypes = [P, C.POINTER(AlOptions)] + [P] * 11
+        L.tron_design_chol.argtypes = [I32, I64, I32, P, P, P, P]
+        L.tron_design_trsv.argtypes = [I32, I64, I32, P, P, P, I32, P]
         L.tron_clock_rate_hz.restype = I64
         L.tron_batch_set_timestamps.argtypes = [P, P]
         L.tron_server_default_config.argtypes = [C.POINTER(ServerConfig)]
@@ -263,6 +267,33 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def design_chol(variant, a, l=None, info=None, stream=None):
+    """Batched Cholesky of a (count, n, n) float64 device tensor of SPD blocks, in one of the
+    design variants of include/tron_design.h. Returns (L, info)."""
+    import torch
+    count, n = int(a.shape[0]), int(a.shape[1])
+    if l is None:
+        l = torch.empty_like(a)
+    if info is None:
+        info = torch.empty(count, dtype=torch.int32, device=a.device)
+    _check(lib().tron_design_chol(variant, count, n, _dev(a, torch.float64, count * n * n, "a"),
+                                  _dev(l, torch.float64, count * n * n, "l"),
+                                  _dev(info, torch.int32, count, "info"), _stream_ptr(stream)))
+    return l, info
+
+
+def design_trsv(variant, l, b, x=None, reps=1, stream=None):
+    """Solve L L^T x = b for (count, n, n) factors and (count, n) right-hand sides."""
+    import torch
+    count, n = int(l.shape[0]), int(l.shape[1])
+    if x is None:
+        x = torch.empty_like(b)
+    _check(lib().tron_design_trsv(variant, count, n, _dev(l, torch.float64, count * n * n, "l"),
+                                  _dev(b, torch.float64, count * n, "b"), _dev(x, torch.float64, count * n, "x"),
+                                  reps, _stream_ptr(stream)))
+    return x
 
 
 def to_device(batch, device="cuda"):

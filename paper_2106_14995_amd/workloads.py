@@ -263,6 +263,22 @@ def hs45m_random_start(batch: int, n, config_id: int = 70) -> Batch:
 
 
 # ------------------------------------------------------------------------------------
+# Dense SPD blocks for the kernel-design microbenchmarks (section 4, Tables 1-2)
+# ------------------------------------------------------------------------------------
+def spd_blocks(count: int, n: int, config_id: int = 80):
+    """(A, b): count SPD matrices A = M'M + n I with M ~ N(0,1)^{n x n} (eigenvalues in
+    about [n, 5n]) and right-hand sides b ~ N(0,1)^n, as float64 arrays (count, n, n), (count, n)."""
+    A = np.empty((count, n, n))
+    B = np.empty((count, n))
+    for p in range(count):
+        r = rng_for(config_id, p)
+        M = r.standard_normal((n, n))
+        A[p] = M.T @ M + n * np.eye(n)
+        B[p] = r.standard_normal(n)
+    return A, B
+
+
+# ------------------------------------------------------------------------------------
 # Network for the component ADMM
 # ------------------------------------------------------------------------------------
 class Network:

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_functions():
-    src = open(os.path.join(ROOT, "include", "tron.h")).read()
+    src = "".join(open(os.path.join(ROOT, "include", h)).read() for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+                  if h.endswith(".h"))
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(",
                        src, flags=re.M)
@@ -45,6 +46,17 @@ def test_host_helpers():
     a = tron.AlOptions()
     tron.lib().tron_default_al_options(C.byref(a))
     assert (a.ctol, a.outer_max, a.rho_growth, a.decrease, a.rho_max) == (1e-6, 50, 10.0, 0.25, 1e6)
+
+
+def test_design_calls_reject_bad_arguments_before_touching_the_device():
+    from paper_2106_14995_amd import tron
+    L = tron.lib()
+    assert L.tron_design_chol(7, 1, 4, None, None, None, None) == 1    # unknown variant
+    assert L.tron_design_chol(0, 1, 65, None, None, None, None) == 1   # n above 64
+    assert L.tron_design_chol(0, 1, 4, None, None, None, None) == 1    # null pointers
+    assert L.tron_design_chol(0, 0, 4, None, None, None, None) == 0    # empty batch
+    assert L.tron_design_trsv(0, 1, 4, None, None, None, 0, None) == 1  # reps < 1
+    assert L.tron_design_trsv(4, 1, 4, None, None, None, 1, None) == 1  # unknown variant
 
 
 def test_al_solve_rejects_bad_arguments_before_touching_the_device():
