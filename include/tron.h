@@ -56,7 +56,7 @@ enum {
 
 /* Problem families. Parameter block sizes (doubles per instance):
  *   QP4:   n(n+1)/2 + n + 1 -- f = x'Qx/2 + c'x + kappa sum x_i^4; packed lower triangle of
- *          Q row by row (Q00 Q10 Q11 Q20 ...), then c, then kappa. 1 <= n <= 128.
+ *          Q row by row (Q00 Q10 Q11 Q20 ...), then c, then kappa. 1 <= n <= 512.
  *   BR6:   36, n = 6 -- the branch subproblem of eq. exp-branch in x = (v_i, v_j, th_i,
  *          th_j, z_ij, z_ji): [0..7] g_ij b_ij gc_ij bc_ij g_ji b_ji gc_ji bc_ji,
  *          [8..15] targets of (p_ij q_ij p_ji q_ji w_i w_j th_i th_j), [16..23] their
@@ -147,8 +147,11 @@ tron_err tron_autotune(tron_family family, int64_t batch, const int32_t *n_host,
 /* Solve every instance (Algorithm 1 per instance). d_x0 (read) and d_x (written) may be the
  * same buffer for an in-place warm start. d_f (batch doubles), d_status and d_iters (batch
  * int32 each) are written. d_params, d_lo, d_hi are read only. Bounds may be +-inf.
- * Instances with n <= 8 are solved one per GPU lane, larger ones one per wavefront; the
- * size buckets run concurrently on the handle's own streams, joined back into `stream`.
+ * Instances with n <= 8 are solved one per GPU lane, larger ones one per wavefront (up to
+ * n = 128 with the Hessian and factor in LDS, beyond that in a global-memory workspace of
+ * n ((n+1)|1) doubles per instance, rounded up to n = 256 or 512, that the handle allocates
+ * at creation); the size buckets run concurrently on the handle's own streams, joined back
+ * into `stream`.
  * Errors: INVALID (null pointers), DEVICE (launch or capture failure). */
 tron_err tron_batch_solve(tron_batch *h, const double *d_params, const double *d_lo,
                           const double *d_hi, const double *d_x0, double *d_x, double *d_f,
@@ -236,7 +239,9 @@ tron_err tron_server_create(tron_server **out, tron_family family, const tron_se
  * the call returns). session != 0 keeps the instances' solution, radius and Cauchy step
  * resident on the device after the solve; a later request of the same session (same sizes)
  * may pass x0 = NULL to start from them. A session holds at most one request at a time.
- * Errors: INVALID, BUSY (larger than the device budget, or its session is busy). */
+ * Instances must have n <= 128 (the server keeps every matrix in LDS).
+ * Errors: INVALID, UNSUPPORTED (n > 128), BUSY (larger than the device budget, or its
+ * session is busy). */
 tron_err tron_server_submit(tron_server *s, int64_t batch, const int32_t *n, const double *params,
                             const double *lo, const double *hi, const double *x0, uint64_t session,
                             int64_t *ticket);

@@ -552,6 +552,10 @@ extern "C" tron_err tron_server_submit(tron_server *s, int64_t batch, const int3
     for (int64_t i = 0; i < batch; i++) {
         const int64_t ps = tron_param_size(s->fam, r->n[i]);
         if (ps < 0) return mt_fail(TRON_ERR_INVALID, "instance %lld: n = %d invalid", (long long)i, r->n[i]);
+        // the server's launch groups keep every matrix in LDS
+        if (r->n[i] > kLdsMaxN)
+            return mt_fail(TRON_ERR_UNSUPPORTED, "instance %lld: n = %d above the server's limit of %d",
+                           (long long)i, r->n[i], kLdsMaxN);
         if (r->n[i] > 8) lds += mt_wave_lds_bytes(wave_nmax_of(r->n[i]));
         nsum += r->n[i];
         psum += ps;

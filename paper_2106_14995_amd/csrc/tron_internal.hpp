@@ -21,7 +21,16 @@ struct LaneArgs {
     int32_t n_uniform, psize;
     int32_t lane_block;      // workgroup size of the lane kernels (64 or 256; 0 means 256)
     mt::Options opt;
+    double *ws;              // n > 128: per-instance matrix workspace in global memory
+    int64_t ws_stride;       // doubles per instance in ws (bucket slot t uses ws + t stride)
 };
+
+// Largest n of any family with a wave kernel; n in (kLdsMaxN, kMaxN] keeps its matrices in a
+// global-memory workspace instead of LDS.
+constexpr int kLdsMaxN = 128;
+constexpr int kMaxN = 512;
+// doubles of one instance's matrix array for bucket size nmax (n rows, odd stride > n)
+inline int64_t mt_wave_matrix_doubles(int nmax) { return (int64_t)nmax * (int64_t)((nmax + 1) | 1); }
 
 typedef void (*lane_launch_fn)(const LaneArgs &, hipStream_t);
 
@@ -30,7 +39,8 @@ void mt_launch_br6(const LaneArgs &a, hipStream_t st);
 // The lane kernel for (family, N <= 8), or null when unsupported.
 lane_launch_fn mt_lane_launcher(tron_family fam, int N);
 // The wavefront-per-instance kernel of the family (QP4 or HS45M) for instances with
-// n <= nmax (nmax <= 128); LDS is sized for nmax.
+// n <= nmax (nmax <= kLdsMaxN: LDS sized for nmax; larger nmax: a.ws must hold a.count
+// slots of a.ws_stride >= mt_wave_matrix_doubles(nmax) doubles).
 void mt_launch_wave(tron_family fam, const LaneArgs &a, int nmax, hipStream_t st);
 // LDS bytes the wave kernel uses for one instance of size n (its bucket's footprint).
 size_t mt_wave_lds_bytes(int nmax);

@@ -51,7 +51,7 @@ extern "C" void tron_default_options(tron_options *o)
 
 extern "C" int64_t tron_param_size(tron_family fam, int32_t n)
 {
-    if (fam == TRON_FAMILY_QP4 && n >= 1 && n <= 128) return (int64_t)n * (n + 1) / 2 + n + 1;
+    if (fam == TRON_FAMILY_QP4 && n >= 1 && n <= kMaxN) return (int64_t)n * (n + 1) / 2 + n + 1;
     if (fam == TRON_FAMILY_BR6 && n == 6) return 36;
     if (fam == TRON_FAMILY_HS45M && n >= 1 && n <= 128) return 0;
     if (fam == TRON_FAMILY_BR8L && n == 8) return 40;
@@ -211,8 +211,8 @@ __global__ __launch_bounds__(kLaneBlock) void al_kernel(LaneArgs a, AlArgs al)
 // wavefront-per-instance kernels (8 < n <= 128; QP4 and HS45M); one 64-lane workgroup per
 // instance, so the hardware dispatcher hands the next instance to whichever CU frees up first
 // ------------------------------------------------------------------------------------
-template <class Fam>
-__global__ __launch_bounds__(64) void wave_kernel(LaneArgs a)
+template <class Fam, bool kGlobal>
+__device__ __forceinline__ void wave_body(const LaneArgs &a)
 {
     extern __shared__ double smem[];
     const int64_t t = blockIdx.x;
@@ -223,11 +223,11 @@ __global__ __launch_bounds__(64) void wave_kernel(LaneArgs a)
     const int64_t vo = a.voff ? a.voff[b] : b * (int64_t)n;
     const int64_t t0 = a.ts ? (int64_t)wall_clock64() : 0;
     constexpr int R = Fam::R;
-    mt::WaveTron<Fam> s;
+    mt::WaveTron<Fam, kGlobal> s;
     s.n = n;
-    s.ld = n | 1;
+    s.ld = (n + 1) | 1;  // odd and > n: column n holds the factor's pivots
     s.lane = threadIdx.x;
-    s.M = smem;
+    s.M = kGlobal ? a.ws + t * a.ws_stride : smem;
     s.load(a.params + po, a.lo + vo, a.hi + vo, a.x0 + vo);
     const double din = a.opt.warm ? a.state[b] : 0.0;
     const double ain = a.opt.warm ? a.state[a.batch + b] : 0.0;
@@ -248,17 +248,50 @@ __global__ __launch_bounds__(64) void wave_kernel(LaneArgs a)
     }
 }
 
-static size_t wave_lds_bytes(int nmax) { return sizeof(double) * (size_t)nmax * (size_t)(nmax | 1); }
+// Two builds of the same solver. Buckets of small n fit many instances per CU, so their
+// kernel keeps its register count low for occupancy. From n_max = kWaveBigN on, the LDS
+// request already limits residency to about two waves per SIMD, so that build is allowed
+// the registers to keep its LDS loads in flight (the factorisation's partial sums then wait
+// once per eight loads instead of once per two).
+constexpr int kWaveBigN = 48;
+
+template <class Fam>
+__global__ __launch_bounds__(64) void wave_kernel(LaneArgs a) { wave_body<Fam, false>(a); }
+
+template <class Fam>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void wave_kernel_big(LaneArgs a)
+{
+    wave_body<Fam, false>(a);
+}
+
+// n > kLdsMaxN: the matrix array is the instance's slot of a global-memory workspace
+template <class Fam>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void wave_kernel_global(LaneArgs a)
+{
+    wave_body<Fam, true>(a);
+}
+
+static size_t wave_lds_bytes(int nmax) { return sizeof(double) * (size_t)nmax * (size_t)((nmax + 1) | 1); }
 
 template <class Fam>
 static void launch_wave(const LaneArgs &a, int nmax, hipStream_t st)
 {
     if (a.count <= 0) return;
     const size_t lds = wave_lds_bytes(nmax);
-    hipLaunchKernelGGL((wave_kernel<Fam>), dim3((unsigned)a.count), dim3(64), lds, st, a);
+    if (nmax >= kWaveBigN)
+        hipLaunchKernelGGL((wave_kernel_big<Fam>), dim3((unsigned)a.count), dim3(64), lds, st, a);
+    else
+        hipLaunchKernelGGL((wave_kernel<Fam>), dim3((unsigned)a.count), dim3(64), lds, st, a);
 }
 
-// the wave kernel of the family for instances with n <= nmax (nmax <= 128)
+template <class Fam>
+static void launch_wave_global(const LaneArgs &a, hipStream_t st)
+{
+    if (a.count <= 0) return;
+    hipLaunchKernelGGL((wave_kernel_global<Fam>), dim3((unsigned)a.count), dim3(64), 0, st, a);
+}
+
+// the wave kernel of the family for instances with n <= nmax
 static void launch_wave_fam(tron_family fam, const LaneArgs &a, int nmax, hipStream_t st)
 {
     using namespace mt;
@@ -267,7 +300,9 @@ static void launch_wave_fam(tron_family fam, const LaneArgs &a, int nmax, hipStr
         else launch_wave<WaveFamHS45M<2>>(a, nmax, st);
     } else {
         if (nmax <= 64) launch_wave<WaveFamQP4<1>>(a, nmax, st);
-        else launch_wave<WaveFamQP4<2>>(a, nmax, st);
+        else if (nmax <= kLdsMaxN) launch_wave<WaveFamQP4<2>>(a, nmax, st);
+        else if (nmax <= 256) launch_wave_global<WaveFamQP4<4>>(a, st);
+        else launch_wave_global<WaveFamQP4<8>>(a, st);
     }
 }
 
@@ -282,7 +317,11 @@ struct Bucket {
     int64_t count;     // instances in the bucket
     int32_t *d_index;  // instance list (null when the bucket is the whole batch in order)
     lane_launch_fn lane;
+    double *d_ws;      // nmax > kLdsMaxN: count slots of mt_wave_matrix_doubles(nmax) doubles
 };
+
+// sizes above the LDS limit go to a global-memory bucket of 256 or kMaxN
+static int global_edge(int n) { return n <= 256 ? 256 : kMaxN; }
 
 lane_launch_fn mt_lane_launcher(tron_family fam, int N) { return lane_launcher(fam, N); }
 void mt_launch_wave(tron_family fam, const LaneArgs &a, int nmax, hipStream_t st)
@@ -294,16 +333,24 @@ void mt_prepare_wave_kernels()
 {
     using namespace mt;
     const int big = (int)wave_lds_bytes(128), small = (int)wave_lds_bytes(64);
-    (void)hipFuncSetAttribute((const void *)wave_kernel<WaveFamQP4<1>>, hipFuncAttributeMaxDynamicSharedMemorySize, small);
-    (void)hipFuncSetAttribute((const void *)wave_kernel<WaveFamQP4<2>>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-    (void)hipFuncSetAttribute((const void *)wave_kernel<WaveFamHS45M<1>>, hipFuncAttributeMaxDynamicSharedMemorySize, small);
-    (void)hipFuncSetAttribute((const void *)wave_kernel<WaveFamHS45M<2>>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    const void *k64[] = {(const void *)wave_kernel<WaveFamQP4<1>>, (const void *)wave_kernel_big<WaveFamQP4<1>>,
+                         (const void *)wave_kernel<WaveFamHS45M<1>>, (const void *)wave_kernel_big<WaveFamHS45M<1>>};
+    const void *k128[] = {(const void *)wave_kernel<WaveFamQP4<2>>, (const void *)wave_kernel_big<WaveFamQP4<2>>,
+                          (const void *)wave_kernel<WaveFamHS45M<2>>, (const void *)wave_kernel_big<WaveFamHS45M<2>>};
+    for (const void *k : k64) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, small);
+    for (const void *k : k128) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }
 
-static void launch_bucket(tron_family fam, const Bucket &b, const LaneArgs &a, hipStream_t st)
+static void launch_bucket(tron_family fam, const Bucket &b, const LaneArgs &a0, hipStream_t st)
 {
-    if (b.lanes == 1) b.lane(a, st);
-    else launch_wave_fam(fam, a, b.nmax, st);
+    if (b.lanes == 1) {
+        b.lane(a0, st);
+        return;
+    }
+    LaneArgs a = a0;
+    a.ws = b.d_ws;
+    a.ws_stride = b.d_ws ? mt_wave_matrix_doubles(b.nmax) : 0;
+    launch_wave_fam(fam, a, b.nmax, st);
 }
 
 static void default_spec(tron_plan_spec *p)
@@ -387,7 +434,10 @@ static void free_batch(tron_batch *h)
     (void)hipFree(h->d_n);
     (void)hipFree(h->d_poff);
     (void)hipFree(h->d_voff);
-    for (auto &b : h->buckets) (void)hipFree(b.d_index);
+    for (auto &b : h->buckets) {
+        (void)hipFree(b.d_index);
+        (void)hipFree(b.d_ws);
+    }
     delete h;
 }
 
@@ -422,6 +472,9 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
             b.nmax = h->n_uniform;
             b.lanes = 64;
             b.lane = nullptr;
+            if (b.nmax > kLdsMaxN &&
+                hipMalloc(&b.d_ws, sizeof(double) * (size_t)mt_wave_matrix_doubles(b.nmax) * (size_t)b.count) != hipSuccess)
+                return mt_fail(TRON_ERR_NOMEM, "matrix workspace allocation failed");
         }
         h->buckets.push_back(b);
         return TRON_OK;
@@ -432,20 +485,24 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
         if (lane_ok(n[i])) lane_lists[n[i]].push_back((int32_t)i);
         else {
             if (!has_wave_kernel(h->fam)) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d has no kernel for this family", n[i]);
-            const int e = spec_edge(sp, n[i]);
+            const int e = n[i] > kLdsMaxN ? global_edge(n[i]) : spec_edge(sp, n[i]);
             if (!e) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d above the largest plan edge", n[i]);
             wave_lists[e].push_back((int32_t)i);
         }
     }
     auto add = [&](std::vector<int32_t> &list, int nmax, int lanes) -> tron_err {
-        Bucket b{};
+        // registered first, so that free_batch releases whatever the allocations below got
+        h->buckets.push_back(Bucket{});
+        Bucket &b = h->buckets.back();
         b.nmax = nmax;
         b.lanes = lanes;
         b.count = (int64_t)list.size();
         b.lane = lanes == 1 ? lane_launcher(h->fam, nmax) : nullptr;
+        if (lanes == 64 && nmax > kLdsMaxN &&
+            hipMalloc(&b.d_ws, sizeof(double) * (size_t)mt_wave_matrix_doubles(nmax) * list.size()) != hipSuccess)
+            return mt_fail(TRON_ERR_NOMEM, "matrix workspace allocation failed");
         HIP_TRY(hipMalloc(&b.d_index, sizeof(int32_t) * list.size()));
         HIP_TRY(hipMemcpyAsync(b.d_index, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, st));
-        h->buckets.push_back(b);
         return TRON_OK;
     };
     for (auto it = wave_lists.rbegin(); it != wave_lists.rend(); ++it) {

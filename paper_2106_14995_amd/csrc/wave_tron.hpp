@@ -1,11 +1,14 @@
-// wave_tron.hpp -- one trust-region Newton solve per wavefront, for 8 < n <= 128.
+// wave_tron.hpp -- one trust-region Newton solve per wavefront, for 8 < n <= 512.
 //
-// Lane l of the wave owns rows i = l and i = l + 64 (R = 2 only for n > 64) of every
-// vector. The n x n Hessian and its Cholesky factor share one LDS array of row stride ld
-// (odd, so that both row and column walks touch distinct banks): the factor L in the lower
-// triangle with its diagonal, the Hessian's strict upper triangle above it; the Hessian's
-// diagonal stays in registers. Every decision of the method is taken on wave-reduced,
-// wave-uniform values (the free set is a 64-bit ballot), so the 64 lanes never diverge.
+// Lane l of the wave owns rows i = l + 64 r, r < R, of every vector (R = 1 up to n = 64, 2 up
+// to 128, then 4 and 8 with the matrix array in global memory). The n x n Hessian and its
+// Cholesky factor share one array (LDS up to n = 128) of n rows and odd
+// row stride ld >= n + 1 (odd, so that both row and column walks touch distinct banks): the
+// Hessian's upper triangle with its diagonal, the factor's strict lower triangle below it,
+// and the factor's pivots in the spare column n. A Hessian-vector product then reads every
+// H_kj from one address, min(j,k) ld + max(j,k), with no special case on the diagonal.
+// Every decision of the method is taken on wave-reduced, wave-uniform values (the free set
+// is a 64-bit ballot), so the 64 lanes never diverge.
 // Sums use a butterfly of lane swaps (every lane ends with the same bits); the pivots and
 // solution components of the triangular solves are broadcast with readlane.
 //
@@ -125,7 +128,11 @@ struct WaveFamQP4 {
     template <class S>
     MT_INLINE void hess(S &s) const
     {
-        MT_UNROLL for (int r = 0; r < R; r++) s.hd[r] = fma(12.0 * kap * s.x[r], s.x[r], qd[r]);
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            s.hd[r] = fma(12.0 * kap * s.x[r], s.x[r], qd[r]);
+            if (s.valid(r)) s.M[s.row(r) * (s.ld + 1)] = s.hd[r];
+        }
+        s.sync();
     }
 };
 
@@ -180,21 +187,38 @@ struct WaveFamHS45M {
                 suf[r] *= i == j ? 1.0 : xj;
             }
         }
-        MT_UNROLL for (int r = 0; r < R; r++) s.hd[r] = 0.0;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            s.hd[r] = 0.0;
+            if (s.valid(r)) s.M[s.row(r) * (ld + 1)] = 0.0;
+        }
+        s.sync();
     }
 };
 
 // One trust-region Newton solve per wave for the family Fam, Fam::R rows per lane
 // (n <= 64 R).
-template <class Fam>
+// kGlobal: the matrix array M lives in global memory (a device workspace, for n > 128)
+// instead of LDS; only the scope of the ordering between the lanes' writes and reads changes.
+template <class Fam, bool kGlobal = false>
 struct WaveTron {
     static constexpr int R = Fam::R;
+
+    // make every lane's writes to M visible to every lane of the wave
+    MT_INLINE void sync() const
+    {
+        if (kGlobal) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
     Fam fam;
     int n, ld, lane;
-    double *M;                 // LDS: L lower with diagonal, H strict upper, row stride ld
+    double *M;                 // LDS: H upper with diagonal, L strict lower, pivots in column n
     double hd[R];              // H diagonal (own rows)
     double lo[R], hi[R], x[R], g[R], xs[R], dinv[R];
     uint64_t lfm[R];           // free set of the last factored pass
@@ -212,15 +236,53 @@ struct WaveTron {
         return uni(wave_sum(s));
     }
 
-    // H_kj for row k (< n) from the upper triangle, diag on the diagonal
+    // LDS index of H_kj (upper triangle, diagonal included): min(j,k) ld + max(j,k), with a
+    // 24-bit multiply-add (indices stay far below 2^24)
+    MT_INLINE int hidx(int k, int j) const
+    {
+        const int a = j < k ? j : k, b = j < k ? k : j;
+        return (int)__umul24((unsigned)a, (unsigned)ld) + b;
+    }
+
+    // H_kj for row k (< n), with diag in place of the stored diagonal
     MT_INLINE double hget(int k, int j, double dg) const
     {
-        const double h = M[j < k ? j * ld + k : k * ld + j];
+        const double h = M[hidx(k, j)];
         return j == k ? dg : h;
     }
 
-    // y = A v over the first n rows, A = H with diagonal diag (Q's or H's); rows >= n give 0.
-    // Four independent accumulators per row; no lane-dependent branches in the loop.
+    // y = H v over the first n rows (H's diagonal read from LDS, as hess() stored it); rows
+    // >= n give 0. Four independent accumulators per row; no lane-dependent branches.
+    MT_INLINE void hmul(const double (&v)[R], double (&y)[R]) const
+    {
+        double acc[R][4];
+        int kk[R];
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
+            kk[r] = row(r) < n ? row(r) : 0;
+        }
+        MT_UNROLL for (int rr = 0; rr < R; rr++) {
+            const int jend = n - 64 * rr < 64 ? n - 64 * rr : 64;
+            int jj = 0;
+            for (; jj + 4 <= jend; jj += 4) {
+                double vj[4];
+                MT_UNROLL for (int u = 0; u < 4; u++) vj[u] = bcast(v[rr], jj + u);
+                MT_UNROLL for (int r = 0; r < R; r++)
+                    MT_UNROLL for (int u = 0; u < 4; u++)
+                        acc[r][u] = fma(M[hidx(kk[r], 64 * rr + jj + u)], vj[u], acc[r][u]);
+            }
+            for (; jj < jend; jj++) {
+                const double vj = bcast(v[rr], jj);
+                MT_UNROLL for (int r = 0; r < R; r++)
+                    acc[r][0] = fma(M[hidx(kk[r], 64 * rr + jj)], vj, acc[r][0]);
+            }
+        }
+        MT_UNROLL for (int r = 0; r < R; r++)
+            y[r] = valid(r) ? (acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3]) : 0.0;
+    }
+
+    // y = A v over the first n rows, A = H's off-diagonal part with diagonal diag (QP4's f
+    // and gradient use Q's diagonal); rows >= n give 0.
     MT_INLINE void amul(const double (&v)[R], const double (&diag)[R], double (&y)[R]) const
     {
         double acc[R][4];
@@ -292,7 +354,14 @@ struct WaveTron {
         return sqrt(uni(wave_sum(s)));
     }
 
-    MT_INLINE bool is_free(const uint64_t (&fm)[R], int j) const { return (fm[j >> 6] >> (j & 63)) & 1ull; }
+    // bit j of a row-distributed mask; a select chain rather than a runtime index, so the
+    // mask stays in registers for every R
+    MT_INLINE bool is_free(const uint64_t (&fm)[R], int j) const
+    {
+        uint64_t w = fm[0];
+        MT_UNROLL for (int r = 1; r < R; r++) w = (j >> 6) == r ? fm[r] : w;
+        return (w >> (j & 63)) & 1ull;
+    }
     MT_INLINE bool own_free(const uint64_t (&fm)[R], int r) const { return (fm[r] >> lane) & 1ull; }
 
     // masked left-looking Cholesky of H_FF + alpha I (identity outside F)
@@ -306,12 +375,13 @@ struct WaveTron {
                 const int i = row(r);
                 const int k = i < n ? i : 0;
                 double a;
-                if (k > j) a = M[j * ld + k];            // H_ij from the upper triangle
+                if (k > j) a = M[hidx(k, j)];            // H_kj from the upper triangle
                 else a = hd[r] + alpha;                   // only used when i == j
                 if (fj && k >= j) {
                     // a -= L_k[0:j] . L_j[0:j], in 8 independent partial sums so the LDS
                     // loads pipeline and the FMA chains are j/8 long
-                    const double *rk = M + k * ld, *rj = M + j * ld;
+                    const double *rk = M + __umul24((unsigned)k, (unsigned)ld);
+                    const double *rj = M + __umul24((unsigned)j, (unsigned)ld);
                     double p[8] = {a, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
                     int q = 0;
                     for (; q + 8 <= j; q += 8) {
@@ -322,21 +392,21 @@ struct WaveTron {
                 }
                 s[r] = a;
             }
-            const double d = uni(bcast(s[rj], lj));
+            double sj = s[0];
+            MT_UNROLL for (int r = 1; r < R; r++) sj = rj == r ? s[r] : sj;
+            const double d = uni(bcast(sj, lj));
             if (fj && !(d > 0.0)) return false;
             const double rinv = fj ? rsqrt(d) : 1.0;
             const double piv = fj ? d * rinv : 1.0;
             MT_UNROLL for (int r = 0; r < R; r++) {
                 const int i = row(r);
-                if (i < n && i > j) M[i * ld + j] = (fj && own_free(fm, r)) ? s[r] * rinv : 0.0;
+                if (i < n && i > j) M[__umul24((unsigned)i, (unsigned)ld) + j] = (fj && own_free(fm, r)) ? s[r] * rinv : 0.0;
                 if (i == j) {
-                    M[i * ld + i] = piv;
+                    M[__umul24((unsigned)i, (unsigned)ld) + n] = piv;
                     dinv[r] = rinv;
                 }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            sync();
         }
         return true;
     }
@@ -361,7 +431,7 @@ struct WaveTron {
         for (int j = 0; j < n; j++) {
             MT_UNROLL for (int r = 0; r < R; r++) {
                 const int i = row(r);
-                if (i < n && i > j) M[i * ld + j] = 0.0;
+                if (i < n && i > j) M[__umul24((unsigned)i, (unsigned)ld) + j] = 0.0;
             }
         }
         MT_UNROLL for (int r = 0; r < R; r++) {
@@ -369,13 +439,11 @@ struct WaveTron {
             if (i < n) {
                 const double v = fabs(hd[r]);
                 const double piv = own_free(fm, r) ? sqrt(v > beta ? v : beta) : 1.0;
-                M[i * ld + i] = piv;
+                M[__umul24((unsigned)i, (unsigned)ld) + n] = piv;
                 dinv[r] = 1.0 / piv;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        sync();
     }
 
     // component j of b * dinv, taken from its owner lane (wave-uniform result)
@@ -394,7 +462,7 @@ struct WaveTron {
             MT_UNROLL for (int r = 0; r < R; r++) {
                 const int i = row(r);
                 const bool below = i > j && i < n;
-                const double l = M[below ? i * ld + j : 0];
+                const double l = M[below ? (int)__umul24((unsigned)i, (unsigned)ld) + j : 0];
                 b[r] = i == j ? yj : (below ? fma(-l, yj, b[r]) : b[r]);
             }
         }
@@ -408,7 +476,7 @@ struct WaveTron {
             MT_UNROLL for (int r = 0; r < R; r++) {
                 const int i = row(r);
                 const bool above = i < j;
-                const double l = M[above ? j * ld + i : 0];
+                const double l = M[above ? (int)__umul24((unsigned)j, (unsigned)ld) + i : 0];
                 b[r] = i == j ? yj : (above ? fma(-l, yj, b[r]) : b[r]);
             }
         }
@@ -433,7 +501,7 @@ struct WaveTron {
             st[r] = xt[r] - x[r];
         }
         if (!(dot(st, st) <= delta * delta)) return false;
-        amul(st, hd, hs);
+        hmul(st, hs);
         double ss[R];
         MT_UNROLL for (int r = 0; r < R; r++) ss[r] = fma(0.5, hs[r], g[r]);
         const double gts = dot(g, st);
@@ -500,7 +568,7 @@ struct WaveTron {
             double z[R], q[R];
             MT_UNROLL for (int r = 0; r < R; r++) z[r] = p[r];
             bwd(z);
-            amul(z, hd, q);
+            hmul(z, q);
             MT_UNROLL for (int r = 0; r < R; r++) q[r] = own_free(fm, r) ? q[r] : 0.0;
             fwd(q);
             const double kap_ = dot(p, q);
@@ -541,7 +609,7 @@ struct WaveTron {
             if (m == 0) break;
             double s[R], rv[R];
             MT_UNROLL for (int r = 0; r < R; r++) s[r] = xs[r] - x[r];
-            amul(s, hd, rv);
+            hmul(s, rv);
             MT_UNROLL for (int r = 0; r < R; r++) rv[r] += g[r];
             precond(fm);
             has_l = true;
@@ -558,7 +626,7 @@ struct WaveTron {
                     xt[r] = clampf(fma(beta, w[r], xs[r]), lo[r], hi[r]);
                     d[r] = xt[r] - xs[r];
                 }
-                amul(d, hd, hdv);
+                hmul(d, hdv);
                 double hh[R];
                 MT_UNROLL for (int r = 0; r < R; r++) hh[r] = fma(0.5, hdv[r], rv[r]);
                 const double rd = dot(rv, d);
@@ -578,15 +646,18 @@ struct WaveTron {
     MT_INLINE double step_norm(const double (&s)[R]) const
     {
         if (!has_l) return sqrt(dot(s, s));
-        // t = L^T s: t_i = sum_{k >= i} L_ki s_k
+        // t = L^T s: t_i = L_ii s_i + sum_{k > i} L_ki s_k (the pivot L_ii sits in column n)
         double t[R];
-        MT_UNROLL for (int r = 0; r < R; r++) t[r] = 0.0;
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const int i = row(r);
+            t[r] = valid(r) ? M[__umul24((unsigned)i, (unsigned)ld) + n] * s[r] : 0.0;
+        }
         for (int k = 0; k < n; k++) {
             const double sk = comp(s, k);
             MT_UNROLL for (int r = 0; r < R; r++) {
                 const int i = row(r);
-                const bool in = i <= k;
-                const double l = M[in ? k * ld + i : 0];
+                const bool in = i < k;
+                const double l = M[in ? (int)__umul24((unsigned)k, (unsigned)ld) + i : 0];
                 t[r] = in ? fma(l, sk, t[r]) : t[r];
             }
         }
@@ -624,9 +695,7 @@ struct WaveTron {
         MT_UNROLL for (int r = 0; r < R; r++) bad = bad || (valid(r) && !(lo[r] <= hi[r]));
         if (__ballot(bad) != 0ull) return kBadBounds;
         MT_UNROLL for (int r = 0; r < R; r++) x[r] = clampb(x[r], lo[r], hi[r]);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        sync();
         f = fg(x, g);
         bool fin = true;
         MT_UNROLL for (int r = 0; r < R; r++) fin = fin && isfinite(g[r]);
@@ -648,7 +717,7 @@ struct WaveTron {
             double s[R], hs[R];
             MT_UNROLL for (int r = 0; r < R; r++) s[r] = xs[r] - x[r];
             const double snorm = step_norm(s);
-            amul(s, hd, hs);
+            hmul(s, hs);
             double hh[R];
             MT_UNROLL for (int r = 0; r < R; r++) hh[r] = fma(0.5, hs[r], g[r]);
             const double gts = dot(g, s);

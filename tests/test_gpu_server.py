@@ -123,6 +123,15 @@ def test_admission_under_a_tight_budget(T):
     srv.close()
 
 
+def test_sizes_above_the_lds_limit_are_refused(T):
+    bt = W.qp4_batch(2, 200, config_id=101)
+    srv = T.Server(W.QP4)
+    with pytest.raises(T.TronError) as e:
+        srv.submit_batch(bt)
+    assert e.value.code == 4  # UNSUPPORTED
+    srv.close()
+
+
 def test_destroy_with_work_pending(T):
     srv = T.Server(W.QP4, max_inflight=2)
     for i in range(6):

@@ -262,6 +262,25 @@ def test_uneven_4_to_128(tron):
     assert {b["lanes"] for b in plan} == {1, 64}
 
 
+@pytest.mark.parametrize("n,count", [(129, 24), (200, 16), (256, 12), (257, 8), (400, 6), (512, 6)])
+def test_qp4_above_lds_sizes(tron, n, count):
+    """n > 128: one wavefront per instance with the Hessian and factor in the handle's
+    global-memory workspace."""
+    bt = W.qp4_batch(count, n, config_id=70 + n)
+    check_parity(bt, gpu_solve(tron, bt), oracle_ref(bt), convex=True)
+
+
+def test_uneven_across_the_lds_limit(tron):
+    sizes = np.array([100, 128, 129, 140, 7, 255, 256, 3, 257, 300, 64, 512, 130, 129], dtype=np.int32)
+    bt = W.qp4_batch(len(sizes), sizes, config_id=77)
+    check_parity(bt, gpu_solve(tron, bt), oracle_ref(bt), convex=True)
+    h = tron.Batch(W.QP4, sizes)
+    plan = h.plan()
+    h.close()
+    assert sum(b["count"] for b in plan) == len(sizes)
+    assert {b["nmax"] for b in plan if b["lanes"] == 64} >= {256, 512}
+
+
 def test_wave_edge_cases(tron):
     n = 20
     bt = W.qp4_batch(4, n, config_id=61)
