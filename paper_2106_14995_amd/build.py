@@ -12,7 +12,10 @@ LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libtron_mi355x.so")
 SOURCES = ["tron_lib.hip", "admm.hip", "server.hip", "design.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# The solver kernels run one wave per SIMD (their register or LDS footprint allows no more),
+# so instruction-level parallelism, not occupancy, hides latency: schedule for ILP.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+         "-mllvm", "-amdgpu-sched-strategy=gcn-max-ilp",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
 

@@ -525,42 +525,25 @@ struct LaneTron {
         return !any || below;
     }
 
-    // The search of reading S4 as one loop with a per-lane phase: the first trial at the
-    // stored step, then either extrapolation (x10 while acceptable and below the last
-    // breakpoint) or interpolation (x0.1 until acceptable), at most kCauchyMax trials in
-    // either phase. Each lane takes exactly the trials of the two-branch form, but the 64
-    // lanes of a wave run their trials in the same loop trips instead of a wave paying for
-    // both branches one after the other when its lanes disagree about the first trial.
     MT_INLINE void cauchy()
     {
-        enum { kFirst = 0, kExtra = 1, kInter = 2, kDone = 3 };
         double a = alphac;
         double xt[N];
-        int phase = kFirst, t = 0;
-        for (int trip = 0; trip <= kCauchyMax; trip++) {
-            if (phase == kExtra && (t >= kCauchyMax || !below_last_breakpoint(a))) phase = kDone;
-            if (phase == kDone) break;
-            const double cand = phase == kFirst ? a : (phase == kExtra ? 10.0 * a : 0.1 * a);
-            const bool ok = cauchy_trial(cand, xt);
-            if (phase == kFirst) {
-                if (ok) MT_UNROLL for (int i = 0; i < N; i++) xs[i] = xt[i];
-                phase = ok ? kExtra : kInter;
-            } else if (phase == kExtra) {
-                t++;
-                if (ok) {
-                    a = cand;
-                    MT_UNROLL for (int i = 0; i < N; i++) xs[i] = xt[i];
-                } else {
-                    phase = kDone;
-                }
-            } else {
-                t++;
-                a = cand;
-                if (ok || t >= kCauchyMax) {
-                    MT_UNROLL for (int i = 0; i < N; i++) xs[i] = xt[i];
-                    phase = kDone;
-                }
+        if (cauchy_trial(a, xt)) {
+            MT_UNROLL for (int i = 0; i < N; i++) xs[i] = xt[i];
+            for (int t = 0; t < kCauchyMax; t++) {
+                if (!below_last_breakpoint(a)) break;
+                const double a2 = 10.0 * a;
+                if (!cauchy_trial(a2, xt)) break;
+                a = a2;
+                MT_UNROLL for (int i = 0; i < N; i++) xs[i] = xt[i];
             }
+        } else {
+            for (int t = 0; t < kCauchyMax; t++) {
+                a = 0.1 * a;
+                if (cauchy_trial(a, xt)) break;
+            }
+            MT_UNROLL for (int i = 0; i < N; i++) xs[i] = xt[i];
         }
         alphac = a;
     }
