@@ -126,6 +126,35 @@ def test_br6_full_size_sampled(tron):
     check_parity(bt, g, oracle_ref(bt, idx), convex=False, idx=idx)
 
 
+def test_uneven_full_size_sampled(tron):
+    """The uneven benchmark's batch (50,000 quartic problems, n log-uniform in [4,64]) in the
+    launch configurations the benchmark times: the default plan captured in a graph and
+    replayed, and the autotuned plan; a sample is re-solved by the oracle and both plans
+    must agree with it."""
+    import torch
+    B = 50000
+    sizes = W.loguniform_sizes(B, 4, 64, config_id=3)
+    bt = W.qp4_batch(B, sizes, config_id=3)
+    dev = tron.to_device(bt)
+    out = dict(x=torch.empty(int(sizes.astype(np.int64).sum()), dtype=torch.float64, device="cuda"),
+               f=torch.empty(B, dtype=torch.float64, device="cuda"),
+               status=torch.empty(B, dtype=torch.int32, device="cuda"),
+               iters=torch.empty(B, dtype=torch.int32, device="cuda"))
+    rng = np.random.default_rng(1)
+    idx = np.sort(np.concatenate([[0, B - 1], rng.choice(B, 800, replace=False)]))
+    ref = oracle_ref(bt, idx)
+    spec, _ = tron.autotune(W.QP4, sizes, *dev, out["x"], out["f"], out["status"], out["iters"], reps=1)
+    for sp in (None, spec):
+        h = tron.Batch(W.QP4, sizes, opts=tron.options(graph=True), spec=sp)
+        for _ in range(3):  # capture, then replays
+            h.solve(*dev, **out)
+        torch.cuda.synchronize()
+        h.close()
+        g = {k: v.cpu().numpy() for k, v in out.items()}
+        assert np.all(g["status"] == 0)
+        check_parity(bt, g, ref, convex=True, idx=idx)
+
+
 def test_br6_zero_residual(tron):
     bt = W.br6_zero_residual(512)
     g = gpu_solve(tron, bt, gtol=1e-9)
