@@ -71,7 +71,10 @@ __device__ inline void couplings(const double *adm, const double *x, double *y)
     y[7] = x[3];
 }
 
-constexpr int kBlock = 256;
+// 64-lane workgroups: the ADMM kernels are a few thousand threads of scattered loads, and one
+// wave per workgroup spreads them over four times as many CUs (and their load pipelines)
+// as 256-lane workgroups would
+constexpr int kBlock = 64;
 
 __global__ __launch_bounds__(kBlock) void admm_init_kernel(Net n, double *s)
 {
@@ -149,70 +152,156 @@ __global__ __launch_bounds__(kBlock) void couplings_kernel(Net n, double *s)
 // bus subproblem: minimise sum w_k/2 (yt_k - t_k)^2, t_k = y_k + lam_k / rho, over the bus
 // copies (generator powers, branch-end flows, w shared by the ends, theta), subject to
 // the two balance rows; yt = t - W^-1 A' (A W^-1 A')^-1 (A t - b)
+// One thread per bus. The state was just written by kernels running on every XCD, so most
+// loads miss this XCD's L2 and each round of dependent loads costs about a microsecond. A bus
+// with at most kFastG generators and kFastE branch ends therefore loads everything it needs
+// in three rounds (its own data and CSR bounds; the neighbour indices; every neighbour value
+// both passes use) and keeps it in registers; larger buses take the general path. Both paths
+// perform the same operations in the same order.
+constexpr int kFastG = 4, kFastE = 16;
+
+struct BusSums {
+    double sgp = 0.0, sgq = 0.0, sep = 0.0, seq = 0.0, sw = 0.0, sth = 0.0;
+};
+
+struct BusSolve {
+    double up, uq, wnew, tnew;
+};
+
+__device__ inline BusSolve bus_solve(const Net &n, int64_t b, const BusSums &t, int ng_, int ne_, const double *ld)
+{
+    const double rho = n.rho;
+    const double ng = (double)ng_, deg = (double)ne_;
+    const double pd = ld[0], qd = ld[1], gs = ld[2], bs = ld[3];
+    const double tw = t.sw / deg, tth = t.sth / deg;
+    const double ww = deg * rho;
+    const double ep = t.sgp - t.sep - gs * tw - pd;
+    const double eq = t.sgq - t.seq + bs * tw - qd;
+    const double mpp = (ng + deg) / rho + gs * gs / ww;
+    const double mqq = (ng + deg) / rho + bs * bs / ww;
+    const double mpq = -gs * bs / ww;
+    const double det = mpp * mqq - mpq * mpq;
+    BusSolve r;
+    r.up = (mqq * ep - mpq * eq) / det;
+    r.uq = (mpp * eq - mpq * ep) / det;
+    r.wnew = tw - (-gs * r.up + bs * r.uq) / ww;
+    r.tnew = b == n.ref ? 0.0 : tth;
+    return r;
+}
+
 __global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *part_dual)
 {
     const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (b >= n.B) return;
     View v = split(s, n.G, n.L, n.B);
     const double rho = n.rho;
-    double sgp = 0.0, sgq = 0.0, sep = 0.0, seq = 0.0, sw = 0.0, sth = 0.0;
     const int g0 = n.bg_ptr[b], g1 = n.bg_ptr[b + 1];
     const int e0 = n.be_ptr[b], e1 = n.be_ptr[b + 1];
-    for (int k = g0; k < g1; k++) {
-        const int g = n.bg_idx[k];
-        sgp += v.pg[g] + v.lpg[g] / rho;
-        sgq += v.qg[g] + v.lqg[g] / rho;
-    }
-    for (int k = e0; k < e1; k++) {
-        const int code = n.be_idx[k];
-        const int64_t l = code >> 1;
-        const int e = code & 1;
-        const double *y = v.y + 8 * l, *la = v.lam + 8 * l;
-        sep += y[2 * e] + la[2 * e] / rho;
-        seq += y[2 * e + 1] + la[2 * e + 1] / rho;
-        sw += y[4 + e] + la[4 + e] / rho;
-        sth += y[6 + e] + la[6 + e] / rho;
-    }
-    const double ng = (double)(g1 - g0), deg = (double)(e1 - e0);
-    const double *ld = n.load + 4 * b;
-    const double pd = ld[0], qd = ld[1], gs = ld[2], bs = ld[3];
-    const double tw = sw / deg, tth = sth / deg;
-    const double ww = deg * rho;
-    const double ep = sgp - sep - gs * tw - pd;
-    const double eq = sgq - seq + bs * tw - qd;
-    const double mpp = (ng + deg) / rho + gs * gs / ww;
-    const double mqq = (ng + deg) / rho + bs * bs / ww;
-    const double mpq = -gs * bs / ww;
-    const double det = mpp * mqq - mpq * mpq;
-    const double up = (mqq * ep - mpq * eq) / det;
-    const double uq = (mpp * eq - mpq * ep) / det;
-    const double wnew = tw - (-gs * up + bs * uq) / ww;
-    const double tnew = b == n.ref ? 0.0 : tth;
+    double ld[4];
+    MT_UNROLL for (int k = 0; k < 4; k++) ld[k] = n.load[4 * b + k];
+    const double wt0 = v.wt[b], tht0 = v.tht[b];
+    const int ng = g1 - g0, ne = e1 - e0;
+    BusSums t;
     double d2 = 0.0;
-    for (int k = g0; k < g1; k++) {
-        const int g = n.bg_idx[k];
-        const double np = v.pg[g] + v.lpg[g] / rho - up / rho;
-        const double nq = v.qg[g] + v.lqg[g] / rho - uq / rho;
-        d2 += (np - v.pgt[g]) * (np - v.pgt[g]) + (nq - v.qgt[g]) * (nq - v.qgt[g]);
-        v.pgt[g] = np;
-        v.qgt[g] = nq;
+    if (ng <= kFastG && ne <= kFastE) {
+        int gi[kFastG], code[kFastE];
+        MT_UNROLL for (int u = 0; u < kFastG; u++) gi[u] = u < ng ? n.bg_idx[g0 + u] : -1;
+        MT_UNROLL for (int u = 0; u < kFastE; u++) code[u] = u < ne ? n.be_idx[e0 + u] : -1;
+        double pg[kFastG], lpg[kFastG], qg[kFastG], lqg[kFastG], pgt[kFastG], qgt[kFastG];
+        MT_UNROLL for (int u = 0; u < kFastG; u++) {
+            const int g = gi[u] < 0 ? 0 : gi[u];
+            pg[u] = v.pg[g]; lpg[u] = v.lpg[g]; qg[u] = v.qg[g]; lqg[u] = v.lqg[g];
+            pgt[u] = v.pgt[g]; qgt[u] = v.qgt[g];
+        }
+        double yp[kFastE], yq[kFastE], yw[kFastE], yth[kFastE], lp[kFastE], lq[kFastE], lw[kFastE], lth[kFastE];
+        double otp[kFastE], otq[kFastE];
+        MT_UNROLL for (int u = 0; u < kFastE; u++) {
+            const int c = code[u] < 0 ? 0 : code[u];
+            const int64_t l = c >> 1;
+            const int e = c & 1;
+            const double *y = v.y + 8 * l, *la = v.lam + 8 * l, *yt = v.yt + 4 * l;
+            yp[u] = y[2 * e]; yq[u] = y[2 * e + 1]; yw[u] = y[4 + e]; yth[u] = y[6 + e];
+            lp[u] = la[2 * e]; lq[u] = la[2 * e + 1]; lw[u] = la[4 + e]; lth[u] = la[6 + e];
+            otp[u] = yt[2 * e]; otq[u] = yt[2 * e + 1];
+        }
+        MT_UNROLL for (int u = 0; u < kFastG; u++)
+            if (u < ng) {
+                t.sgp += pg[u] + lpg[u] / rho;
+                t.sgq += qg[u] + lqg[u] / rho;
+            }
+        MT_UNROLL for (int u = 0; u < kFastE; u++)
+            if (u < ne) {
+                t.sep += yp[u] + lp[u] / rho;
+                t.seq += yq[u] + lq[u] / rho;
+                t.sw += yw[u] + lw[u] / rho;
+                t.sth += yth[u] + lth[u] / rho;
+            }
+        const BusSolve r = bus_solve(n, b, t, ng, ne, ld);
+        MT_UNROLL for (int u = 0; u < kFastG; u++)
+            if (u < ng) {
+                const double np = pg[u] + lpg[u] / rho - r.up / rho;
+                const double nq = qg[u] + lqg[u] / rho - r.uq / rho;
+                d2 += (np - pgt[u]) * (np - pgt[u]) + (nq - qgt[u]) * (nq - qgt[u]);
+                v.pgt[gi[u]] = np;
+                v.qgt[gi[u]] = nq;
+            }
+        const double dw = r.wnew - wt0, dt = r.tnew - tht0;
+        MT_UNROLL for (int u = 0; u < kFastE; u++)
+            if (u < ne) {
+                const int64_t l = code[u] >> 1;
+                const int e = code[u] & 1;
+                const double np = yp[u] + lp[u] / rho + r.up / rho;
+                const double nq = yq[u] + lq[u] / rho + r.uq / rho;
+                d2 += (np - otp[u]) * (np - otp[u]) + (nq - otq[u]) * (nq - otq[u]);
+                d2 += dw * dw + dt * dt;
+                double *yt = v.yt + 4 * l;
+                yt[2 * e] = np;
+                yt[2 * e + 1] = nq;
+            }
+        v.wt[b] = r.wnew;
+        v.tht[b] = r.tnew;
+    } else {
+        for (int k = g0; k < g1; k++) {
+            const int g = n.bg_idx[k];
+            t.sgp += v.pg[g] + v.lpg[g] / rho;
+            t.sgq += v.qg[g] + v.lqg[g] / rho;
+        }
+        for (int k = e0; k < e1; k++) {
+            const int code = n.be_idx[k];
+            const int64_t l = code >> 1;
+            const int e = code & 1;
+            const double *y = v.y + 8 * l, *la = v.lam + 8 * l;
+            t.sep += y[2 * e] + la[2 * e] / rho;
+            t.seq += y[2 * e + 1] + la[2 * e + 1] / rho;
+            t.sw += y[4 + e] + la[4 + e] / rho;
+            t.sth += y[6 + e] + la[6 + e] / rho;
+        }
+        const BusSolve r = bus_solve(n, b, t, ng, ne, ld);
+        for (int k = g0; k < g1; k++) {
+            const int g = n.bg_idx[k];
+            const double np = v.pg[g] + v.lpg[g] / rho - r.up / rho;
+            const double nq = v.qg[g] + v.lqg[g] / rho - r.uq / rho;
+            d2 += (np - v.pgt[g]) * (np - v.pgt[g]) + (nq - v.qgt[g]) * (nq - v.qgt[g]);
+            v.pgt[g] = np;
+            v.qgt[g] = nq;
+        }
+        const double dw = r.wnew - wt0, dt = r.tnew - tht0;
+        for (int k = e0; k < e1; k++) {
+            const int code = n.be_idx[k];
+            const int64_t l = code >> 1;
+            const int e = code & 1;
+            const double *y = v.y + 8 * l, *la = v.lam + 8 * l;
+            double *yt = v.yt + 4 * l;
+            const double np = y[2 * e] + la[2 * e] / rho + r.up / rho;
+            const double nq = y[2 * e + 1] + la[2 * e + 1] / rho + r.uq / rho;
+            d2 += (np - yt[2 * e]) * (np - yt[2 * e]) + (nq - yt[2 * e + 1]) * (nq - yt[2 * e + 1]);
+            d2 += dw * dw + dt * dt;
+            yt[2 * e] = np;
+            yt[2 * e + 1] = nq;
+        }
+        v.wt[b] = r.wnew;
+        v.tht[b] = r.tnew;
     }
-    const double dw = wnew - v.wt[b], dt = tnew - v.tht[b];
-    for (int k = e0; k < e1; k++) {
-        const int code = n.be_idx[k];
-        const int64_t l = code >> 1;
-        const int e = code & 1;
-        const double *y = v.y + 8 * l, *la = v.lam + 8 * l;
-        double *yt = v.yt + 4 * l;
-        const double np = y[2 * e] + la[2 * e] / rho + up / rho;
-        const double nq = y[2 * e + 1] + la[2 * e + 1] / rho + uq / rho;
-        d2 += (np - yt[2 * e]) * (np - yt[2 * e]) + (nq - yt[2 * e + 1]) * (nq - yt[2 * e + 1]);
-        d2 += dw * dw + dt * dt;
-        yt[2 * e] = np;
-        yt[2 * e + 1] = nq;
-    }
-    v.wt[b] = wnew;
-    v.tht[b] = tnew;
     part_dual[b] = d2;
 }
 
@@ -422,6 +511,7 @@ extern "C" tron_err admm_step(admm *a, int32_t iters, double *d_resid, void *str
     la.opt.delta0 = a->opt.delta0;
     la.opt.max_iter = a->opt.max_iter;
     la.opt.warm = 1;
+    la.lane_block = 64;  // a few thousand branches: one wave per workgroup, spread over more CUs
     double *part_primal = a->d_part, *part_dual = a->d_part + n.G + n.L;
     for (int32_t it = 0; it < iters; it++) {
         hipLaunchKernelGGL(gen_pack_kernel, dim3(grid_for((int64_t)n.G + n.L)), dim3(kBlock), 0, st, n,
