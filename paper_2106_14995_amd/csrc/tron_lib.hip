@@ -256,7 +256,7 @@ __device__ __forceinline__ void wave_body(const LaneArgs &a)
 constexpr int kWaveBigN = 48;
 
 template <class Fam>
-__global__ __launch_bounds__(64) void wave_kernel(LaneArgs a) { wave_body<Fam, false>(a); }
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void wave_kernel(LaneArgs a) { wave_body<Fam, false>(a); }
 
 template <class Fam>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void wave_kernel_big(LaneArgs a)

@@ -364,8 +364,145 @@ struct WaveTron {
     }
     MT_INLINE bool own_free(const uint64_t (&fm)[R], int r) const { return (fm[r] >> lane) & 1ull; }
 
-    // masked left-looking Cholesky of H_FF + alpha I (identity outside F)
+    // Cholesky factor of H_FF + alpha I with the identity outside F: the factor's strict lower
+    // triangle into M's lower part, its pivots into column n, their reciprocals into dinv.
+    // False when a pivot of a free column is not positive (the caller then raises alpha).
     MT_INLINE bool chol(const uint64_t (&fm)[R], double alpha)
+    {
+        if constexpr (kGlobal) return chol_columns(fm, alpha);
+        else return chol_panels(fm, alpha);
+    }
+
+    // Entry (k, j), k >= j, of H_FF + alpha I with the identity outside F, and 0 above the
+    // diagonal and outside the first n rows and columns. k and j may differ between lanes.
+    MT_INLINE double shifted(const uint64_t (&fm)[R], int k, int j, double alpha) const
+    {
+        const bool in = k < n && j < n && k >= j;
+        // H_jk from the upper triangle; the address is clamped rather than branched on
+        const double h = M[in ? (int)__umul24((unsigned)j, (unsigned)ld) + k : 0];
+        const bool fj = is_free(fm, j);
+        const double e = k == j ? (fj ? h + alpha : 1.0) : ((fj && is_free(fm, k)) ? h : 0.0);
+        return in ? e : 0.0;
+    }
+
+    // Factor the 16 columns j0 .. j0 + 15 of S (left in the factor's slots, its diagonal in
+    // column n), each lane holding its rows in registers, left-looking inside the panel and
+    // pipelined by one column: while column c takes its pivot, column c + 1 already subtracts
+    // the panel's columns before c, reading row j0 + c + 1 of the factor from LDS at one
+    // address in every lane (a broadcast read of entries that are final since the last step);
+    // only column c's own contribution waits for c, with the entry L(j0+c+1, j0+c) read from
+    // its owner lane. Each scaled entry goes straight to its final slot in LDS.
+    MT_INLINE bool panel_factor(const uint64_t (&fm)[R], int j0)
+    {
+        const int rp = j0 >> 6;  // register slot of the panel's rows
+        double sv[R][16];
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const int i = row(r);
+            MT_UNROLL for (int c = 0; c < 16; c++) {
+                const int j = j0 + c;
+                const bool in = i < n && i >= j;
+                const double v = M[in ? (int)__umul24((unsigned)i, (unsigned)ld) + (i == j ? n : j) : 0];
+                sv[r][c] = in ? v : 0.0;
+            }
+        }
+        // A non-positive free pivot is remembered and reported once the panel is done. Column
+        // c + 1 may lie past n (then it is prepared from row 0 and never used).
+        bool bad = false;
+        MT_UNROLL for (int c = 0; c < 16; c++) {
+            const int j = j0 + c;
+            if (j >= n) break;
+            double pre[16];
+            if (c + 1 < 16) {
+                const int jn = j + 1 < n ? j + 1 : 0;
+                const double *rn = M + __umul24((unsigned)jn, (unsigned)ld) + j0;
+                MT_UNROLL for (int c1 = 0; c1 < c; c1++) pre[c1] = rn[c1];
+            }
+            if (c > 0) {
+                double lv = sv[0][c - 1];
+                MT_UNROLL for (int r = 1; r < R; r++) lv = rp == r ? sv[r][c - 1] : lv;
+                const double l = bcast(lv, j & 63);
+                MT_UNROLL for (int r = 0; r < R; r++) sv[r][c] = fma(-sv[r][c - 1], l, sv[r][c]);
+            }
+            const bool fj = is_free(fm, j);
+            double sj = sv[0][c];
+            MT_UNROLL for (int r = 1; r < R; r++) sj = rp == r ? sv[r][c] : sj;
+            const double d = uni(bcast(sj, j & 63));
+            bad = bad || (fj && !(d > 0.0));
+            const double rinv = fj ? rsqrt(d) : 1.0;
+            const double piv = fj ? d * rinv : 1.0;
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = row(r);
+                sv[r][c] = (fj && own_free(fm, r)) ? sv[r][c] * rinv : 0.0;
+                if (i < n && i > j) M[__umul24((unsigned)i, (unsigned)ld) + j] = sv[r][c];
+                if (i == j && j < n) {
+                    M[__umul24((unsigned)j, (unsigned)ld) + n] = piv;
+                    dinv[r] = rinv;
+                }
+            }
+            if (c + 1 < 16) {
+                MT_UNROLL for (int r = 0; r < R; r++) {
+                    double p0 = sv[r][c + 1], p1 = 0.0;
+                    MT_UNROLL for (int c1 = 0; c1 < c; c1++) {
+                        if (c1 & 1) p1 = fma(-sv[r][c1], pre[c1], p1);
+                        else p0 = fma(-sv[r][c1], pre[c1], p0);
+                    }
+                    sv[r][c + 1] = p0 + p1;
+                }
+            }
+            sync();
+        }
+        return !bad;
+    }
+
+    // Blocked left-looking factorisation in panels of 16 columns. For the panel starting at
+    // column j0, the matrix cores form S = A[j0:n, panel] - L[j0:n, 0:j0] L[panel, 0:j0]^T,
+    // 16 x 16 blocks by 16 x 16 x 4 FP64 products (operands read from LDS once, no
+    // broadcasts); then each lane factors its rows of S in registers, column by column, with
+    // the pivot and the panel's own factor entries broadcast by readlane. One wave barrier per
+    // phase instead of one per column.
+    // Lane layout of the 16 x 16 x 4 FP64 product: A(i, k) in lane i + 16 k, B(k, j) in lane
+    // j + 16 k, C(i, j) in lane j + 16 (i mod 4), element i / 4 of the lane's four.
+    MT_INLINE bool chol_panels(const uint64_t (&fm)[R], double alpha)
+    {
+        typedef double d4 __attribute__((ext_vector_type(4)));
+        const int lr = lane & 15, lq = lane >> 4;
+        for (int j0 = 0; j0 < n; j0 += 16) {
+            const int jb = j0 + lr;  // this lane's panel column (B row, C column)
+            const int jbk = jb < n ? jb : 0;
+            for (int k0 = j0; k0 < n; k0 += 16) {
+                const int ka = k0 + lr;  // this lane's A row
+                const int kak = ka < n ? ka : 0;
+                d4 acc0, acc1 = {0.0, 0.0, 0.0, 0.0};
+                MT_UNROLL for (int v = 0; v < 4; v++) acc0[v] = shifted(fm, k0 + lq + 4 * v, jb, alpha);
+                const double *ra = M + __umul24((unsigned)kak, (unsigned)ld) + lq;
+                const double *rb = M + __umul24((unsigned)jbk, (unsigned)ld) + lq;
+                // rows past n read row 0 (always present) and use 0
+                const bool ain = ka < n, bin = jb < n;
+                int q0 = 0;
+                for (; q0 + 8 <= j0; q0 += 8) {
+                    const double a0 = ra[q0], b0 = rb[q0], a1 = ra[q0 + 4], b1 = rb[q0 + 4];
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ain ? -a0 : 0.0, bin ? b0 : 0.0, acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ain ? -a1 : 0.0, bin ? b1 : 0.0, acc1, 0, 0, 0);
+                }
+                if (q0 < j0) {
+                    const double a0 = ra[q0], b0 = rb[q0];
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ain ? -a0 : 0.0, bin ? b0 : 0.0, acc0, 0, 0, 0);
+                }
+                MT_UNROLL for (int v = 0; v < 4; v++) {
+                    const int k = k0 + lq + 4 * v;
+                    // S below the diagonal into the factor's slots, its diagonal into column n
+                    if (k < n && jb < n && k >= jb)
+                        M[__umul24((unsigned)k, (unsigned)ld) + (k == jb ? n : jb)] = acc0[v] + acc1[v];
+                }
+            }
+            sync();
+            if (!panel_factor(fm, j0)) return false;
+        }
+        return true;
+    }
+
+    // the same factor one column at a time (left-looking), for a workspace in global memory
+    MT_INLINE bool chol_columns(const uint64_t (&fm)[R], double alpha)
     {
         for (int j = 0; j < n; j++) {
             const int rj = j >> 6, lj = j & 63;
