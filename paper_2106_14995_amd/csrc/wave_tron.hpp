@@ -63,6 +63,17 @@ MT_INLINE double bcast(double v, int src)
     return __hiloint2double(hi, lo);
 }
 
+// 1/sqrt(d) for a positive finite d: the hardware estimate y (about single precision) and
+// one third-order correction from the binomial series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ...
+// with e = 1 - d y^2, which leaves a relative error of order e^3. Four dependent operations
+// after the estimate; a pivot of the factorisation is on a serial chain, so this matters.
+MT_INLINE double rsqrt_pos(double d)
+{
+    const double y = __builtin_amdgcn_rsq(d);
+    const double e = fma(-(d * y), y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 MT_INLINE double max_nan(double a, double b) { return (b > a || b != b) ? b : a; }  // NaN propagates
 
 MT_INLINE double wave_max(double v)
@@ -387,17 +398,21 @@ struct WaveTron {
 
     // Factor the 16 columns j0 .. j0 + 15 of S (left in the factor's slots, its diagonal in
     // column n), each lane holding its rows in registers, left-looking inside the panel and
-    // pipelined by one column: while column c takes its pivot, column c + 1 already subtracts
-    // the panel's columns before c, reading row j0 + c + 1 of the factor from LDS at one
-    // address in every lane (a broadcast read of entries that are final since the last step);
-    // only column c's own contribution waits for c, with the entry L(j0+c+1, j0+c) read from
-    // its owner lane. Each scaled entry goes straight to its final slot in LDS.
+    // pipelined by one column. The serial chain per column is kept to: the pivot lane's own
+    // diagonal update, one readlane of the pivot, the reciprocal square root and the scale.
+    // Beside it, the other rows subtract column c - 1 (its entry in row j0 + c read from the
+    // pivot lane), and column c + 1 subtracts the panel's columns before c, reading row
+    // j0 + c + 1 of the factor from LDS at one address in every lane (a broadcast read of
+    // entries final since the last step). Each scaled entry goes straight to its slot in LDS
+    // (one unconditional-path store per column, so the wait for the broadcast reads never
+    // covers it); the pivots are stored once, after the panel.
     MT_INLINE bool panel_factor(const uint64_t (&fm)[R], int j0)
     {
         const int rp = j0 >> 6;  // register slot of the panel's rows
-        double sv[R][16];
+        double sv[R][16], pv[R];
         MT_UNROLL for (int r = 0; r < R; r++) {
             const int i = row(r);
+            pv[r] = 1.0;
             MT_UNROLL for (int c = 0; c < 16; c++) {
                 const int j = j0 + c;
                 const bool in = i < n && i >= j;
@@ -417,27 +432,27 @@ struct WaveTron {
                 const double *rn = M + __umul24((unsigned)jn, (unsigned)ld) + j0;
                 MT_UNROLL for (int c1 = 0; c1 < c; c1++) pre[c1] = rn[c1];
             }
+            double own = sv[0][c], prev = c > 0 ? sv[0][c - 1] : 0.0;
+            MT_UNROLL for (int r = 1; r < R; r++) {
+                own = rp == r ? sv[r][c] : own;
+                prev = rp == r ? sv[r][c - (c > 0)] : prev;
+            }
+            if (c > 0) own = fma(-prev, prev, own);  // in the pivot lane: S_jj less L_j,j-1^2
+            const double d = uni(bcast(own, j & 63));
             if (c > 0) {
-                double lv = sv[0][c - 1];
-                MT_UNROLL for (int r = 1; r < R; r++) lv = rp == r ? sv[r][c - 1] : lv;
-                const double l = bcast(lv, j & 63);
+                const double l = bcast(prev, j & 63);
                 MT_UNROLL for (int r = 0; r < R; r++) sv[r][c] = fma(-sv[r][c - 1], l, sv[r][c]);
             }
             const bool fj = is_free(fm, j);
-            double sj = sv[0][c];
-            MT_UNROLL for (int r = 1; r < R; r++) sj = rp == r ? sv[r][c] : sj;
-            const double d = uni(bcast(sj, j & 63));
             bad = bad || (fj && !(d > 0.0));
-            const double rinv = fj ? rsqrt(d) : 1.0;
+            const double rinv = fj ? rsqrt_pos(fj ? d : 1.0) : 1.0;  // branch-free
             const double piv = fj ? d * rinv : 1.0;
             MT_UNROLL for (int r = 0; r < R; r++) {
                 const int i = row(r);
                 sv[r][c] = (fj && own_free(fm, r)) ? sv[r][c] * rinv : 0.0;
+                pv[r] = i == j ? piv : pv[r];
+                dinv[r] = i == j ? rinv : dinv[r];
                 if (i < n && i > j) M[__umul24((unsigned)i, (unsigned)ld) + j] = sv[r][c];
-                if (i == j && j < n) {
-                    M[__umul24((unsigned)j, (unsigned)ld) + n] = piv;
-                    dinv[r] = rinv;
-                }
             }
             if (c + 1 < 16) {
                 MT_UNROLL for (int r = 0; r < R; r++) {
@@ -451,6 +466,11 @@ struct WaveTron {
             }
             sync();
         }
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const int i = row(r);
+            if (i >= j0 && i < j0 + 16 && i < n) M[__umul24((unsigned)i, (unsigned)ld) + n] = pv[r];
+        }
+        sync();
         return !bad;
     }
 
