@@ -269,7 +269,7 @@ def bench_design(args):
     count, reps = 10000, 8
     stream = torch.cuda.current_stream()
     chol_names = {tron.CHOL_LEFT_LDS: "left_lds", tron.CHOL_RIGHT_LDS: "right_lds",
-                  tron.CHOL_LEFT_GLOBAL: "left_global"}
+                  tron.CHOL_LEFT_GLOBAL: "left_global", tron.CHOL_BLOCKED_MFMA: "blocked_mfma"}
     trsv_names = {tron.TRSV_IMPLICIT: "implicit_stride_n", tron.TRSV_PADDED: "implicit_stride_odd",
                   tron.TRSV_EXPLICIT: "explicit_lt", tron.TRSV_GLOBAL: "global"}
     rows = []

@@ -24,17 +24,22 @@
 extern "C" {
 #endif
 
-/* Cholesky variants (section 4.3, Table 1). */
+/* Cholesky variants (section 4.3, Table 1, and the solver's own form). */
 enum {
-    TRON_CHOL_LEFT_LDS = 0,    /* left-looking: column j gathers the updates of columns < j  */
-    TRON_CHOL_RIGHT_LDS = 1,   /* right-looking: column j updates the trailing submatrix     */
-    TRON_CHOL_LEFT_GLOBAL = 2  /* left-looking, working in global memory (no LDS)           */
+    TRON_CHOL_LEFT_LDS = 0,     /* left-looking: column j gathers the updates of columns < j */
+    TRON_CHOL_RIGHT_LDS = 1,    /* right-looking: column j updates the trailing submatrix    */
+    TRON_CHOL_LEFT_GLOBAL = 2,  /* left-looking, working in global memory (no LDS)          */
+    TRON_CHOL_BLOCKED_MFMA = 3  /* the solver's factorisation: 16-column panels, each formed
+                                   by FP64 matrix-core products from the columns before it
+                                   and factored in registers (LDS, the solver's layout)      */
 };
 
 /* A = L L^T for each SPD block of d_a (read only). d_l receives L (lower triangle with the
  * diagonal; the strict upper triangle is zeroed). d_info[p] = 0, or j + 1 when pivot j of
- * problem p is not positive (then L holds the columns before j). The LDS variants stage the
- * matrix with an odd row stride (n | 1). */
+ * problem p is not positive or not a number (then L holds the columns before j; with
+ * TRON_CHOL_BLOCKED_MFMA only those before j's panel of 16 are meaningful). The LDS
+ * variants stage the matrix with an odd row stride (n | 1, and (n + 1) | 1 for the blocked
+ * variant, whose spare column n holds the pivots). */
 tron_err tron_design_chol(int32_t variant, int64_t count, int32_t n, const double *d_a,
                           double *d_l, int32_t *d_info, void *stream);
 

@@ -107,7 +107,31 @@ __global__ __launch_bounds__(64) void chol_kernel(int variant, int64_t count, in
     const double *A = a + p * n * n;
     double *Lp = l + p * n * n;
     int rc;
-    if (variant == TRON_CHOL_LEFT_GLOBAL) {
+    if (variant == TRON_CHOL_BLOCKED_MFMA) {
+        // the solver's layout: the matrix's upper triangle with its diagonal at row stride
+        // (n + 1) | 1, the factor's strict lower triangle below it, its pivots in column n
+        mt::WaveTron<mt::WaveFamQP4<1>, false> s;
+        s.n = n;
+        s.ld = (n + 1) | 1;
+        s.lane = threadIdx.x;
+        s.M = sm;
+        for (int e = threadIdx.x; e < n * n; e += 64) {
+            const int r = e / n, c = e - r * n;
+            if (c >= r) sm[r * s.ld + c] = A[e];
+        }
+        wave_sync();
+        const uint64_t fm[1] = {n == 64 ? ~0ull : (1ull << n) - 1ull};
+        const bool ok = s.chol(fm, 0.0);
+        wave_sync();
+        for (int e = threadIdx.x; e < n * n; e += 64) {
+            const int r = e / n, c = e - r * n;
+            Lp[e] = c < r ? sm[r * s.ld + c] : (c == r ? sm[r * s.ld + n] : 0.0);
+        }
+        // the first pivot that is not positive: every pivot before it was
+        const int i = threadIdx.x;
+        const uint64_t badp = __ballot(i < n && !(sm[(i < n ? i : 0) * s.ld + n] > 0.0));
+        rc = ok ? 0 : (badp ? __builtin_ctzll(badp) + 1 : 1);
+    } else if (variant == TRON_CHOL_LEFT_GLOBAL) {
         stage_lower(Lp, n, A, n);
         wave_sync_global();
         rc = chol_left<true>(Lp, n, n);
@@ -195,11 +219,12 @@ __global__ __launch_bounds__(64) void trsv_kernel(int variant, int64_t count, in
 extern "C" tron_err tron_design_chol(int32_t variant, int64_t count, int32_t n, const double *d_a,
                                      double *d_l, int32_t *d_info, void *stream)
 {
-    if (variant < TRON_CHOL_LEFT_LDS || variant > TRON_CHOL_LEFT_GLOBAL || count < 0 || n < 1 || n > 64)
+    if (variant < TRON_CHOL_LEFT_LDS || variant > TRON_CHOL_BLOCKED_MFMA || count < 0 || n < 1 || n > 64)
         return mt_fail(TRON_ERR_INVALID, "invalid Cholesky benchmark arguments");
     if (count == 0) return TRON_OK;
     if (!d_a || !d_l || !d_info) return mt_fail(TRON_ERR_INVALID, "null device pointer");
-    const size_t lds = variant == TRON_CHOL_LEFT_GLOBAL ? 0 : sizeof(double) * (size_t)n * (size_t)(n | 1);
+    const size_t stride = variant == TRON_CHOL_BLOCKED_MFMA ? (size_t)((n + 1) | 1) : (size_t)(n | 1);
+    const size_t lds = variant == TRON_CHOL_LEFT_GLOBAL ? 0 : sizeof(double) * (size_t)n * stride;
     hipLaunchKernelGGL(chol_kernel, dim3((unsigned)count), dim3(64), lds, (hipStream_t)stream, (int)variant,
                        count, (int)n, d_a, d_l, d_info);
     HIP_TRY(hipGetLastError());

@@ -70,7 +70,7 @@ EXPORTS = ("tron_default_options", "tron_last_error", "tron_param_size", "tron_b
            "tron_server_stats", "tron_server_destroy", "tron_batch_set_timestamps", "tron_clock_rate_hz",
            "tron_default_plan_spec", "tron_batch_create_ex", "tron_autotune",
            "tron_default_al_options", "tron_al_solve", "tron_design_chol", "tron_design_trsv")
-CHOL_LEFT_LDS, CHOL_RIGHT_LDS, CHOL_LEFT_GLOBAL = 0, 1, 2
+CHOL_LEFT_LDS, CHOL_RIGHT_LDS, CHOL_LEFT_GLOBAL, CHOL_BLOCKED_MFMA = 0, 1, 2, 3
 TRSV_IMPLICIT, TRSV_PADDED, TRSV_EXPLICIT, TRSV_GLOBAL = 0, 1, 2, 3
 
 

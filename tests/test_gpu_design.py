@@ -4,8 +4,8 @@ oracle's substitutions, failure reporting on indefinite blocks, and repetition i
 
 Tolerances: the blocks are A = M'M + n I (condition number below ~5), so the factor and the
 solution are determined to a few units of rounding; different summation orders (the oracle
-sums left to right without FMA, the kernels in four partial sums with FMA) then differ by
-at most ~n eps relative. The bar is 1e-12 relative, with the residual ||L L' - A|| below
+sums left to right without FMA, the kernels in partial sums with FMA or in the matrix
+cores' 16 x 16 x 4 products) then differ by at most ~n eps relative. The bar is 1e-12 relative, with the residual ||L L' - A|| below
 1e-13 ||A||."""
 import numpy as np
 import pytest
@@ -14,7 +14,7 @@ import oracle
 from paper_2106_14995_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
-SIZES = [1, 2, 3, 7, 8, 16, 31, 32, 33, 64]
+SIZES = [1, 2, 3, 7, 8, 15, 16, 17, 31, 32, 33, 47, 48, 49, 63, 64]
 
 
 @pytest.fixture(scope="module")
@@ -39,7 +39,7 @@ def test_cholesky_variants_match_the_oracle(T, n):
     for p in range(A.shape[0]):
         rc, ref[p] = oracle.ccf(A[p])
         assert rc == 0
-    for variant in (T.CHOL_LEFT_LDS, T.CHOL_RIGHT_LDS, T.CHOL_LEFT_GLOBAL):
+    for variant in (T.CHOL_LEFT_LDS, T.CHOL_RIGHT_LDS, T.CHOL_LEFT_GLOBAL, T.CHOL_BLOCKED_MFMA):
         L, info = T.design_chol(variant, dev(A))
         torch.cuda.synchronize()
         L, info = L.cpu().numpy(), info.cpu().numpy()
@@ -60,7 +60,7 @@ def test_cholesky_reports_the_failing_pivot(T, n):
         j = int(rng.integers(0, n))
         A[p, j, j] = -1.0 - A[p, j, j]       # column j's pivot becomes negative
     want = [oracle.ccf(A[p])[0] for p in range(A.shape[0])]
-    for variant in (T.CHOL_LEFT_LDS, T.CHOL_RIGHT_LDS, T.CHOL_LEFT_GLOBAL):
+    for variant in (T.CHOL_LEFT_LDS, T.CHOL_RIGHT_LDS, T.CHOL_LEFT_GLOBAL, T.CHOL_BLOCKED_MFMA):
         _, info = T.design_chol(variant, dev(A))
         torch.cuda.synchronize()
         assert list(info.cpu().numpy()) == want, variant
