@@ -228,6 +228,7 @@ __device__ __forceinline__ void wave_body(const LaneArgs &a)
     s.ld = (n + 1) | 1;  // odd and > n: column n holds the factor's pivots
     s.lane = threadIdx.x;
     s.M = kGlobal ? a.ws + t * a.ws_stride : smem;
+    s.P = kGlobal ? smem : nullptr;
     s.load(a.params + po, a.lo + vo, a.hi + vo, a.x0 + vo);
     const double din = a.opt.warm ? a.state[b] : 0.0;
     const double ain = a.opt.warm ? a.state[a.batch + b] : 0.0;
@@ -249,10 +250,9 @@ __device__ __forceinline__ void wave_body(const LaneArgs &a)
 }
 
 // Two builds of the same solver. Buckets of small n fit many instances per CU, so their
-// kernel keeps its register count low for occupancy. From n_max = kWaveBigN on, the LDS
-// request already limits residency to about two waves per SIMD, so that build is allowed
-// the registers to keep its LDS loads in flight (the factorisation's partial sums then wait
-// once per eight loads instead of once per two).
+// kernel is held to three waves per SIMD's worth of registers. From n_max = kWaveBigN on,
+// the LDS request already limits residency to about two waves per SIMD, so that build gets
+// the registers it asks for.
 constexpr int kWaveBigN = 48;
 
 template <class Fam>
@@ -264,7 +264,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     wave_body<Fam, false>(a);
 }
 
-// n > kLdsMaxN: the matrix array is the instance's slot of a global-memory workspace
+// n > kLdsMaxN: the matrix array is the instance's slot of a global-memory workspace; the
+// LDS holds one 16 x 16 block of the factor while its panel is factored
+constexpr size_t kPanelScratchBytes = sizeof(double) * 16 * 17;
+
 template <class Fam>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void wave_kernel_global(LaneArgs a)
 {
@@ -288,7 +291,7 @@ template <class Fam>
 static void launch_wave_global(const LaneArgs &a, hipStream_t st)
 {
     if (a.count <= 0) return;
-    hipLaunchKernelGGL((wave_kernel_global<Fam>), dim3((unsigned)a.count), dim3(64), 0, st, a);
+    hipLaunchKernelGGL((wave_kernel_global<Fam>), dim3((unsigned)a.count), dim3(64), kPanelScratchBytes, st, a);
 }
 
 // the wave kernel of the family for instances with n <= nmax

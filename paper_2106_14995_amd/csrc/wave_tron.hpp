@@ -214,6 +214,14 @@ template <class Fam, bool kGlobal = false>
 struct WaveTron {
     static constexpr int R = Fam::R;
 
+    // order LDS writes before other lanes' LDS reads (the wave's LDS operations run in order)
+    MT_INLINE void lds_sync() const
+    {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+
     // make every lane's writes to M visible to every lane of the wave
     MT_INLINE void sync() const
     {
@@ -230,6 +238,8 @@ struct WaveTron {
     Fam fam;
     int n, ld, lane;
     double *M;                 // LDS: H upper with diagonal, L strict lower, pivots in column n
+    double *P;                 // with M in global memory: LDS copy of a panel's 16 x 16 block
+                               // of L (row stride 17), so that its columns meet at wave scope
     double hd[R];              // H diagonal (own rows)
     double lo[R], hi[R], x[R], g[R], xs[R], dinv[R];
     uint64_t lfm[R];           // free set of the last factored pass
@@ -380,7 +390,7 @@ struct WaveTron {
     // False when a pivot of a free column is not positive (the caller then raises alpha).
     MT_INLINE bool chol(const uint64_t (&fm)[R], double alpha)
     {
-        if constexpr (kGlobal) return chol_columns(fm, alpha);
+        if constexpr (kGlobal && R > 4) return chol_columns(fm, alpha);
         else return chol_panels(fm, alpha);
     }
 
@@ -429,7 +439,7 @@ struct WaveTron {
             double pre[16];
             if (c + 1 < 16) {
                 const int jn = j + 1 < n ? j + 1 : 0;
-                const double *rn = M + __umul24((unsigned)jn, (unsigned)ld) + j0;
+                const double *rn = kGlobal ? P + (c + 1) * 17 : M + __umul24((unsigned)jn, (unsigned)ld) + j0;
                 MT_UNROLL for (int c1 = 0; c1 < c; c1++) pre[c1] = rn[c1];
             }
             double own = sv[0][c], prev = c > 0 ? sv[0][c - 1] : 0.0;
@@ -453,6 +463,7 @@ struct WaveTron {
                 pv[r] = i == j ? piv : pv[r];
                 dinv[r] = i == j ? rinv : dinv[r];
                 if (i < n && i > j) M[__umul24((unsigned)i, (unsigned)ld) + j] = sv[r][c];
+                if (kGlobal && r == rp && i > j && i < j0 + 16) P[(i - j0) * 17 + c] = sv[r][c];
             }
             if (c + 1 < 16) {
                 MT_UNROLL for (int r = 0; r < R; r++) {
@@ -464,7 +475,8 @@ struct WaveTron {
                     sv[r][c + 1] = p0 + p1;
                 }
             }
-            sync();
+            if constexpr (kGlobal) lds_sync();
+            else sync();
         }
         MT_UNROLL for (int r = 0; r < R; r++) {
             const int i = row(r);
