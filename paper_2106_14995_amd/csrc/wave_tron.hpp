@@ -390,8 +390,7 @@ struct WaveTron {
     // False when a pivot of a free column is not positive (the caller then raises alpha).
     MT_INLINE bool chol(const uint64_t (&fm)[R], double alpha)
     {
-        if constexpr (kGlobal && R > 4) return chol_columns(fm, alpha);
-        else return chol_panels(fm, alpha);
+        return chol_panels(fm, alpha);
     }
 
     // Entry (k, j), k >= j, of H_FF + alpha I with the identity outside F, and 0 above the
@@ -439,7 +438,7 @@ struct WaveTron {
             double pre[16];
             if (c + 1 < 16) {
                 const int jn = j + 1 < n ? j + 1 : 0;
-                const double *rn = kGlobal ? P + (c + 1) * 17 : M + __umul24((unsigned)jn, (unsigned)ld) + j0;
+                const double *rn = M + __umul24((unsigned)jn, (unsigned)ld) + j0;
                 MT_UNROLL for (int c1 = 0; c1 < c; c1++) pre[c1] = rn[c1];
             }
             double own = sv[0][c], prev = c > 0 ? sv[0][c - 1] : 0.0;
@@ -463,7 +462,6 @@ struct WaveTron {
                 pv[r] = i == j ? piv : pv[r];
                 dinv[r] = i == j ? rinv : dinv[r];
                 if (i < n && i > j) M[__umul24((unsigned)i, (unsigned)ld) + j] = sv[r][c];
-                if (kGlobal && r == rp && i > j && i < j0 + 16) P[(i - j0) * 17 + c] = sv[r][c];
             }
             if (c + 1 < 16) {
                 MT_UNROLL for (int r = 0; r < R; r++) {
@@ -475,12 +473,93 @@ struct WaveTron {
                     sv[r][c + 1] = p0 + p1;
                 }
             }
-            if constexpr (kGlobal) lds_sync();
-            else sync();
+            sync();
         }
         MT_UNROLL for (int r = 0; r < R; r++) {
             const int i = row(r);
             if (i >= j0 && i < j0 + 16 && i < n) M[__umul24((unsigned)i, (unsigned)ld) + n] = pv[r];
+        }
+        sync();
+        return !bad;
+    }
+
+    // The same panel step with M in global memory (4 or 8 rows per lane), in two passes that
+    // keep 16 values per lane live instead of 16 per row slot. First the register slot that
+    // holds the panel's rows, pipelined as above, with the panel's 16 x 16 block of L and its
+    // pivot reciprocals mirrored in LDS (P, row stride 17, reciprocal in column 16) so that
+    // its columns meet at wave scope; then every later slot by a triangular solve against
+    // that block, its entries read from LDS at one address in every lane.
+    MT_INLINE bool panel_factor_split(const uint64_t (&fm)[R], int j0)
+    {
+        const int rp = j0 >> 6;
+        const int i = lane + 64 * rp;
+        const bool ownf = i < n && is_free(fm, i);
+        double sv[16], pv = 1.0, dv = 1.0;
+        MT_UNROLL for (int c = 0; c < 16; c++) {
+            const int j = j0 + c;
+            const bool in = i < n && i >= j;
+            const double v = M[in ? (int)__umul24((unsigned)i, (unsigned)ld) + (i == j ? n : j) : 0];
+            sv[c] = in ? v : 0.0;
+        }
+        bool bad = false;
+        MT_UNROLL for (int c = 0; c < 16; c++) {
+            const int j = j0 + c;
+            if (j >= n) break;
+            double pre[16];
+            if (c + 1 < 16) MT_UNROLL for (int c1 = 0; c1 < c; c1++) pre[c1] = P[(c + 1) * 17 + c1];
+            double own = sv[c];
+            if (c > 0) own = fma(-sv[c - 1], sv[c - 1], own);
+            const double d = uni(bcast(own, j & 63));
+            if (c > 0) {
+                const double l = bcast(sv[c - 1], j & 63);
+                sv[c] = fma(-sv[c - 1], l, sv[c]);
+            }
+            const bool fj = is_free(fm, j);
+            bad = bad || (fj && !(d > 0.0));
+            const double rinv = fj ? rsqrt_pos(fj ? d : 1.0) : 1.0;
+            const double piv = fj ? d * rinv : 1.0;
+            sv[c] = (fj && ownf) ? sv[c] * rinv : 0.0;
+            pv = i == j ? piv : pv;
+            dv = i == j ? rinv : dv;
+            if (i < n && i > j) M[__umul24((unsigned)i, (unsigned)ld) + j] = sv[c];
+            if (i > j && i < j0 + 16) P[(i - j0) * 17 + c] = sv[c];
+            if (lane == 0) P[c * 17 + 16] = rinv;
+            if (c + 1 < 16) {
+                double p0 = sv[c + 1], p1 = 0.0;
+                MT_UNROLL for (int c1 = 0; c1 < c; c1++) {
+                    if (c1 & 1) p1 = fma(-sv[c1], pre[c1], p1);
+                    else p0 = fma(-sv[c1], pre[c1], p0);
+                }
+                sv[c + 1] = p0 + p1;
+            }
+            lds_sync();
+        }
+        const bool inp = i >= j0 && i < j0 + 16 && i < n;
+        if (inp) M[__umul24((unsigned)i, (unsigned)ld) + n] = pv;
+        MT_UNROLL for (int r = 0; r < R; r++) dinv[r] = (r == rp && inp) ? dv : dinv[r];
+        // rows of the later slots: L(i, j0 + c) = (S(i, j0 + c) - sum_{c1 < c} L(i, j0 + c1)
+        // L(j0 + c, j0 + c1)) / L(j0 + c, j0 + c)
+        for (int r2 = rp + 1; r2 < R && 64 * r2 < n; r2++) {
+            const int i2 = lane + 64 * r2;
+            const bool in2 = i2 < n;
+            const bool f2 = in2 && is_free(fm, i2);
+            const int base = (int)__umul24((unsigned)(in2 ? i2 : 0), (unsigned)ld) + j0;
+            double t[16];
+            MT_UNROLL for (int c = 0; c < 16; c++) {
+                const double v = M[base + c];
+                t[c] = in2 ? v : 0.0;
+            }
+            MT_UNROLL for (int c = 0; c < 16; c++) {
+                if (j0 + c >= n) break;
+                double p0 = t[c], p1 = 0.0;
+                MT_UNROLL for (int c1 = 0; c1 < c; c1++) {
+                    const double l = P[c * 17 + c1];
+                    if (c1 & 1) p1 = fma(-t[c1], l, p1);
+                    else p0 = fma(-t[c1], l, p0);
+                }
+                t[c] = (is_free(fm, j0 + c) && f2) ? (p0 + p1) * P[c * 17 + 16] : 0.0;
+                if (in2) M[base + c] = t[c];
+            }
         }
         sync();
         return !bad;
@@ -528,7 +607,11 @@ struct WaveTron {
                 }
             }
             sync();
-            if (!panel_factor(fm, j0)) return false;
+            if constexpr (kGlobal) {
+                if (!panel_factor_split(fm, j0)) return false;
+            } else {
+                if (!panel_factor(fm, j0)) return false;
+            }
         }
         return true;
     }
