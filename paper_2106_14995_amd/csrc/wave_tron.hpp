@@ -10,7 +10,9 @@
 // Every decision of the method is taken on wave-reduced, wave-uniform values (the free set
 // is a 64-bit ballot), so the 64 lanes never diverge.
 // Sums use a butterfly of lane swaps (every lane ends with the same bits); the pivots and
-// solution components of the triangular solves are broadcast with readlane.
+// solution components of the triangular solves are broadcast with readlane. The Cholesky
+// factorisation is blocked in panels of 16 columns: FP64 matrix-core products form each
+// panel from the columns before it, and the panel is factored in registers (chol_panels).
 //
 // The steps and readings are those of lane_tron.hpp (Algorithm 1 with the TRON ratio test,
 // the step measured in the trust region's norm, and the trapezoid reduction near rounding
@@ -612,53 +614,6 @@ struct WaveTron {
             } else {
                 if (!panel_factor(fm, j0)) return false;
             }
-        }
-        return true;
-    }
-
-    // the same factor one column at a time (left-looking), for a workspace in global memory
-    MT_INLINE bool chol_columns(const uint64_t (&fm)[R], double alpha)
-    {
-        for (int j = 0; j < n; j++) {
-            const int rj = j >> 6, lj = j & 63;
-            const bool fj = is_free(fm, j);
-            double s[R];
-            MT_UNROLL for (int r = 0; r < R; r++) {
-                const int i = row(r);
-                const int k = i < n ? i : 0;
-                double a;
-                if (k > j) a = M[hidx(k, j)];            // H_kj from the upper triangle
-                else a = hd[r] + alpha;                   // only used when i == j
-                if (fj && k >= j) {
-                    // a -= L_k[0:j] . L_j[0:j], in 8 independent partial sums so the LDS
-                    // loads pipeline and the FMA chains are j/8 long
-                    const double *rk = M + __umul24((unsigned)k, (unsigned)ld);
-                    const double *rj = M + __umul24((unsigned)j, (unsigned)ld);
-                    double p[8] = {a, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                    int q = 0;
-                    for (; q + 8 <= j; q += 8) {
-                        MT_UNROLL for (int u = 0; u < 8; u++) p[u] = fma(-rk[q + u], rj[q + u], p[u]);
-                    }
-                    for (; q < j; q++) p[0] = fma(-rk[q], rj[q], p[0]);
-                    a = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
-                }
-                s[r] = a;
-            }
-            double sj = s[0];
-            MT_UNROLL for (int r = 1; r < R; r++) sj = rj == r ? s[r] : sj;
-            const double d = uni(bcast(sj, lj));
-            if (fj && !(d > 0.0)) return false;
-            const double rinv = fj ? rsqrt(d) : 1.0;
-            const double piv = fj ? d * rinv : 1.0;
-            MT_UNROLL for (int r = 0; r < R; r++) {
-                const int i = row(r);
-                if (i < n && i > j) M[__umul24((unsigned)i, (unsigned)ld) + j] = (fj && own_free(fm, r)) ? s[r] * rinv : 0.0;
-                if (i == j) {
-                    M[__umul24((unsigned)i, (unsigned)ld) + n] = piv;
-                    dinv[r] = rinv;
-                }
-            }
-            sync();
         }
         return true;
     }
