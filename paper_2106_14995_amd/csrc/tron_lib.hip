@@ -281,10 +281,16 @@ static void launch_wave(const LaneArgs &a, int nmax, hipStream_t st)
 {
     if (a.count <= 0) return;
     const size_t lds = wave_lds_bytes(nmax);
-    if (nmax >= kWaveBigN)
+    // two rows per lane means n_max > 64: always the low-occupancy build (the other is never
+    // instantiated for it)
+    if constexpr (Fam::R > 1) {
         hipLaunchKernelGGL((wave_kernel_big<Fam>), dim3((unsigned)a.count), dim3(64), lds, st, a);
-    else
-        hipLaunchKernelGGL((wave_kernel<Fam>), dim3((unsigned)a.count), dim3(64), lds, st, a);
+    } else {
+        if (nmax >= kWaveBigN)
+            hipLaunchKernelGGL((wave_kernel_big<Fam>), dim3((unsigned)a.count), dim3(64), lds, st, a);
+        else
+            hipLaunchKernelGGL((wave_kernel<Fam>), dim3((unsigned)a.count), dim3(64), lds, st, a);
+    }
 }
 
 template <class Fam>
@@ -338,8 +344,7 @@ void mt_prepare_wave_kernels()
     const int big = (int)wave_lds_bytes(128), small = (int)wave_lds_bytes(64);
     const void *k64[] = {(const void *)wave_kernel<WaveFamQP4<1>>, (const void *)wave_kernel_big<WaveFamQP4<1>>,
                          (const void *)wave_kernel<WaveFamHS45M<1>>, (const void *)wave_kernel_big<WaveFamHS45M<1>>};
-    const void *k128[] = {(const void *)wave_kernel<WaveFamQP4<2>>, (const void *)wave_kernel_big<WaveFamQP4<2>>,
-                          (const void *)wave_kernel<WaveFamHS45M<2>>, (const void *)wave_kernel_big<WaveFamHS45M<2>>};
+    const void *k128[] = {(const void *)wave_kernel_big<WaveFamQP4<2>>, (const void *)wave_kernel_big<WaveFamHS45M<2>>};
     for (const void *k : k64) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, small);
     for (const void *k : k128) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
 }

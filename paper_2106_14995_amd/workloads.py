@@ -128,6 +128,22 @@ def qp4_batch(batch: int, n, config_id: int = 0, kappa: float = 0.1, first: int 
     return Batch(QP4, ns, cat(ps), cat(ls), cat(hs), cat(xs))
 
 
+def qp4_half_rank_batch(batch: int, n: int, config_id: int = 90, kappa: float = 0.1) -> Batch:
+    """QP4 with Q = A'A for a Gaussian A of n // 2 rows (rank n // 2): with the quartic term f
+    stays strictly convex, but its Hessian at the start x0 = 0 is Q itself, singular, so the
+    first factorisations meet non-positive pivots and the shifted retries run."""
+    ps, ls, hs, xs = [], [], [], []
+    for b in range(batch):
+        rng = rng_for(config_id, b)
+        a = rng.standard_normal((n // 2, n)) / np.sqrt(n)
+        q = a.T @ a
+        c = rng.standard_normal(n)
+        ps.append(np.concatenate([q[np.tril_indices(n)], c, [kappa]]))
+        ls.append(np.full(n, -2.0)); hs.append(np.full(n, 2.0)); xs.append(np.zeros(n))
+    return Batch(QP4, np.full(batch, n, dtype=np.int32), np.concatenate(ps), np.concatenate(ls),
+                 np.concatenate(hs), np.concatenate(xs))
+
+
 def loguniform_sizes(batch: int, nmin: int, nmax: int, config_id: int, salt: int = 7777777):
     """n_b = clamp(round(exp(U[ln nmin, ln nmax]))), one draw per instance."""
     out = np.empty(batch, dtype=np.int32)
