@@ -661,7 +661,11 @@ struct WaveTron {
         return bcast(v, j & 63);
     }
 
-    // L y = b in place (b zero outside the factored set stays zero); branch-free steps
+    // L y = b in place (b zero outside the factored set stays zero). Each row keeps its
+    // residual unscaled while the substitution runs and is scaled by its reciprocal pivot once
+    // at the end (the value its own step would have taken): the step's chain is then the
+    // owner's scaling, the broadcast and one FMA, with no select on it. Rows not below the
+    // step subtract an exact zero.
     MT_INLINE void fwd(double (&b)[R]) const
     {
         for (int j = 0; j < n; j++) {
@@ -670,12 +674,13 @@ struct WaveTron {
                 const int i = row(r);
                 const bool below = i > j && i < n;
                 const double l = M[below ? (int)__umul24((unsigned)i, (unsigned)ld) + j : 0];
-                b[r] = i == j ? yj : (below ? fma(-l, yj, b[r]) : b[r]);
+                b[r] = fma(-(below ? l : 0.0), yj, b[r]);
             }
         }
+        MT_UNROLL for (int r = 0; r < R; r++) b[r] = valid(r) ? b[r] * dinv[r] : b[r];
     }
 
-    // L^T y = b in place
+    // L^T y = b in place, the same way
     MT_INLINE void bwd(double (&b)[R]) const
     {
         for (int j = n - 1; j >= 0; j--) {
@@ -684,9 +689,10 @@ struct WaveTron {
                 const int i = row(r);
                 const bool above = i < j;
                 const double l = M[above ? (int)__umul24((unsigned)j, (unsigned)ld) + i : 0];
-                b[r] = i == j ? yj : (above ? fma(-l, yj, b[r]) : b[r]);
+                b[r] = fma(-(above ? l : 0.0), yj, b[r]);
             }
         }
+        MT_UNROLL for (int r = 0; r < R; r++) b[r] = valid(r) ? b[r] * dinv[r] : b[r];
     }
 
     MT_INLINE double trqsol(const double (&v)[R], const double (&p)[R]) const
