@@ -859,22 +859,39 @@ struct WaveTron {
     MT_INLINE double step_norm(const double (&s)[R]) const
     {
         if (!has_l) return sqrt(dot(s, s));
-        // t = L^T s: t_i = L_ii s_i + sum_{k > i} L_ki s_k (the pivot L_ii sits in column n)
-        double t[R];
-        MT_UNROLL for (int r = 0; r < R; r++) {
-            const int i = row(r);
-            t[r] = valid(r) ? M[__umul24((unsigned)i, (unsigned)ld) + n] * s[r] : 0.0;
+        // t = L^T s: t_i = L_ii s_i + sum_{k > i} L_ki s_k (the pivot L_ii sits in column n), in
+        // four independent partial sums, four broadcasts and loads at a time (entries of rows
+        // not below i are read as exact zeros, no selects)
+        double acc[R][4];
+        MT_UNROLL for (int r = 0; r < R; r++) acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
+        int k = 0;
+        for (; k + 4 <= n; k += 4) {
+            double sk[4];
+            MT_UNROLL for (int u = 0; u < 4; u++) sk[u] = comp(s, k + u);
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = row(r);
+                MT_UNROLL for (int u = 0; u < 4; u++) {
+                    const bool in = i < k + u;
+                    const double l = M[in ? (int)__umul24((unsigned)(k + u), (unsigned)ld) + i : 0];
+                    acc[r][u] = fma(in ? l : 0.0, sk[u], acc[r][u]);
+                }
+            }
         }
-        for (int k = 0; k < n; k++) {
+        for (; k < n; k++) {
             const double sk = comp(s, k);
             MT_UNROLL for (int r = 0; r < R; r++) {
                 const int i = row(r);
                 const bool in = i < k;
                 const double l = M[in ? (int)__umul24((unsigned)k, (unsigned)ld) + i : 0];
-                t[r] = in ? fma(l, sk, t[r]) : t[r];
+                acc[r][0] = fma(in ? l : 0.0, sk, acc[r][0]);
             }
         }
-        MT_UNROLL for (int r = 0; r < R; r++) t[r] = valid(r) ? t[r] : 0.0;
+        double t[R];
+        MT_UNROLL for (int r = 0; r < R; r++) {
+            const int i = row(r);
+            const double piv = M[valid(r) ? (int)__umul24((unsigned)i, (unsigned)ld) + n : 0];
+            t[r] = valid(r) ? fma(piv, s[r], (acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3])) : 0.0;
+        }
         return sqrt(dot(t, t));
     }
 
