@@ -222,6 +222,34 @@ def bench_hs45m(args):
           flush=True)
 
 
+def bench_large(args):
+    """QP4 beyond the LDS limit (n > 128): one wavefront per instance with the Hessian and its
+    factor in the handle's global-memory workspace, 512 instances per size. Each batch takes
+    tens to hundreds of milliseconds, so at most 3 timed steps per size."""
+    import torch
+    from paper_2106_14995_amd import tron
+    from paper_2106_14995_amd import workloads as W
+    stream = torch.cuda.current_stream()
+    B = 512
+    steps, warmup = min(args.steps, 3), min(args.warmup, 1)
+    rows = []
+    for n in (136, 200, 256, 300, 512):
+        log(f"generating {B} QP4 instances, n = {n}")
+        bt = W.qp4_batch(B, n, config_id=3)
+        h = tron.Batch(W.QP4, n, batch=B)
+        dev = tron.to_device(bt)
+        lat, total = time_solves(lambda: h.solve(*dev, stream=stream), steps, warmup, stream)
+        _, f, st, it = h.solve(*dev, stream=stream)
+        torch.cuda.synchronize()
+        rows.append({"n": n, "ms_per_batch_p50": float(np.median(lat)), "solves_per_s": B * steps / total,
+                     "converged": int((st == 0).sum().item()), "iters_mean": float(it.double().mean().item())})
+        log(f"n={n}: {rows[-1]['ms_per_batch_p50']:.1f} ms per batch")
+        h.close()
+        del dev
+    print(json.dumps({"config": f"QP4, {B} instances per size, n > 128 (global-memory workspace), gtol 1e-6",
+                      "rows": rows}), flush=True)
+
+
 def bench_al(args):
     """Augmented-Lagrangian loop on branch subproblems with line limits (BR8L, n = 8): every
     instance runs its own multiplier loop on the device (ctol 1e-6, gtol 1e-6). Each step
@@ -387,7 +415,7 @@ def main():
     ap.add_argument("--mode", default="br6", choices=["br6", "copy"],
                     help="copy: a plain device-to-device copy of known size, used to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters")
-    ap.add_argument("--config", default="br6", choices=["br6", "qp4", "uneven", "admm", "serve", "hs45m", "al", "design"],
+    ap.add_argument("--config", default="br6", choices=["br6", "qp4", "uneven", "admm", "serve", "hs45m", "al", "design", "large"],
                     help="br6: the headline batch (default); qp4: 256 x n=8 quartic problems "
                          "(oracle CPU seconds and GPU time); uneven: 50,000 quartic problems with "
                          "n log-uniform in [4,64], bucketed graph vs one launch per size; admm: "
@@ -422,7 +450,7 @@ def main():
         return
     if args.config != "br6":
         {"qp4": bench_qp4, "uneven": bench_uneven, "admm": bench_admm, "serve": bench_serve,
-         "hs45m": bench_hs45m, "al": bench_al, "design": bench_design}[args.config](args)
+         "hs45m": bench_hs45m, "al": bench_al, "design": bench_design, "large": bench_large}[args.config](args)
         return
     log(f"generating {args.batch} BR6 instances")
     bt = W.br6_batch(args.batch, config_id=1)
