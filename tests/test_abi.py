@@ -52,6 +52,9 @@ def test_design_calls_reject_bad_arguments_before_touching_the_device():
     from paper_2106_14995_amd import tron
     L = tron.lib()
     assert L.tron_design_chol(7, 1, 4, None, None, None, None) == 1    # unknown variant
+    assert L.tron_design_chol(4, 1, 4, None, None, None, None) == 1    # one past the last
+    assert L.tron_design_chol(tron.CHOL_BLOCKED_MFMA, 0, 64, None, None, None, None) == 0  # valid, empty
+    assert L.tron_design_chol(tron.CHOL_BLOCKED_MFMA, 1, 4, None, None, None, None) == 1  # null pointers
     assert L.tron_design_chol(0, 1, 65, None, None, None, None) == 1   # n above 64
     assert L.tron_design_chol(0, 1, 4, None, None, None, None) == 1    # null pointers
     assert L.tron_design_chol(0, 0, 4, None, None, None, None) == 0    # empty batch
