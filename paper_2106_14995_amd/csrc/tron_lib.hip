@@ -258,6 +258,15 @@ constexpr int kWaveBigN = 48;
 template <class Fam>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void wave_kernel(LaneArgs a) { wave_body<Fam, false>(a); }
 
+// n_max <= kWaveTinyN: the LDS request (8.4 KB at 32) allows four or more instances per SIMD,
+// so this build is held to four waves' worth of registers
+constexpr int kWaveTinyN = 32;
+template <class Fam>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void wave_kernel_tiny(LaneArgs a)
+{
+    wave_body<Fam, false>(a);
+}
+
 template <class Fam>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void wave_kernel_big(LaneArgs a)
 {
@@ -288,8 +297,10 @@ static void launch_wave(const LaneArgs &a, int nmax, hipStream_t st)
     } else {
         if (nmax >= kWaveBigN)
             hipLaunchKernelGGL((wave_kernel_big<Fam>), dim3((unsigned)a.count), dim3(64), lds, st, a);
-        else
+        else if (nmax > kWaveTinyN)
             hipLaunchKernelGGL((wave_kernel<Fam>), dim3((unsigned)a.count), dim3(64), lds, st, a);
+        else
+            hipLaunchKernelGGL((wave_kernel_tiny<Fam>), dim3((unsigned)a.count), dim3(64), lds, st, a);
     }
 }
 
@@ -343,7 +354,8 @@ void mt_prepare_wave_kernels()
     using namespace mt;
     const int big = (int)wave_lds_bytes(128), small = (int)wave_lds_bytes(64);
     const void *k64[] = {(const void *)wave_kernel<WaveFamQP4<1>>, (const void *)wave_kernel_big<WaveFamQP4<1>>,
-                         (const void *)wave_kernel<WaveFamHS45M<1>>, (const void *)wave_kernel_big<WaveFamHS45M<1>>};
+                         (const void *)wave_kernel<WaveFamHS45M<1>>, (const void *)wave_kernel_big<WaveFamHS45M<1>>,
+                         (const void *)wave_kernel_tiny<WaveFamQP4<1>>, (const void *)wave_kernel_tiny<WaveFamHS45M<1>>};
     const void *k128[] = {(const void *)wave_kernel_big<WaveFamQP4<2>>, (const void *)wave_kernel_big<WaveFamHS45M<2>>};
     for (const void *k : k64) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, small);
     for (const void *k : k128) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
