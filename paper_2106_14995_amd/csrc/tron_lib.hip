@@ -229,6 +229,7 @@ __device__ __forceinline__ void wave_body(const LaneArgs &a)
     s.lane = threadIdx.x;
     s.M = kGlobal ? a.ws + t * a.ws_stride : smem;
     s.P = kGlobal ? smem : nullptr;
+    s.Q = kGlobal ? smem + 16 * 17 : nullptr;
     s.load(a.params + po, a.lo + vo, a.hi + vo, a.x0 + vo);
     const double din = a.opt.warm ? a.state[b] : 0.0;
     const double ain = a.opt.warm ? a.state[a.batch + b] : 0.0;
@@ -276,6 +277,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 // n > kLdsMaxN: the matrix array is the instance's slot of a global-memory workspace; the
 // LDS holds one 16 x 16 block of the factor while its panel is factored
 constexpr size_t kPanelScratchBytes = sizeof(double) * 16 * 17;
+// and the substitutions park kStage steps of each lane's entries of L there (R rows each)
+template <class Fam>
+constexpr size_t global_lds_bytes()
+{
+    return kPanelScratchBytes + sizeof(double) * mt::WaveTron<Fam, true>::kStage * Fam::R * 64;
+}
 
 template <class Fam>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 2))) void wave_kernel_global(LaneArgs a)
@@ -308,7 +315,7 @@ template <class Fam>
 static void launch_wave_global(const LaneArgs &a, hipStream_t st)
 {
     if (a.count <= 0) return;
-    hipLaunchKernelGGL((wave_kernel_global<Fam>), dim3((unsigned)a.count), dim3(64), kPanelScratchBytes, st, a);
+    hipLaunchKernelGGL((wave_kernel_global<Fam>), dim3((unsigned)a.count), dim3(64), global_lds_bytes<Fam>(), st, a);
 }
 
 // the wave kernel of the family for instances with n <= nmax

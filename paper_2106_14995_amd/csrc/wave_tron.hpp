@@ -242,6 +242,9 @@ struct WaveTron {
     double *M;                 // LDS: H upper with diagonal, L strict lower, pivots in column n
     double *P;                 // with M in global memory: LDS copy of a panel's 16 x 16 block
                                // of L (row stride 17), so that its columns meet at wave scope
+    double *Q;                 // with M in global memory: kStage steps of each lane's entries of
+                               // L, parked in LDS by the substitutions (slot (t R + r) 64 + lane)
+    static constexpr int kStage = R >= 8 ? 4 : 8;  // 32 values in flight per lane
     double hd[R];              // H diagonal (own rows)
     double lo[R], hi[R], x[R], g[R], xs[R], dinv[R];
     uint64_t lfm[R];           // free set of the last factored pass
@@ -668,13 +671,34 @@ struct WaveTron {
     // step subtract an exact zero.
     MT_INLINE void fwd(double (&b)[R]) const
     {
-        for (int j = 0; j < n; j++) {
-            const double yj = owner_scaled(b, j);
-            MT_UNROLL for (int r = 0; r < R; r++) {
-                const int i = row(r);
-                const bool below = i > j && i < n;
-                const double l = M[below ? (int)__umul24((unsigned)i, (unsigned)ld) + j : 0];
-                b[r] = fma(-(below ? l : 0.0), yj, b[r]);
+        if constexpr (kGlobal) {
+            // M in global memory: the lane's entries of L for kStage steps are loaded together
+            // (one trip to L2 per kStage steps instead of one per step) and parked in the lane's
+            // own LDS slots, which only it reads back
+            for (int j0 = 0; j0 < n; j0 += kStage) {
+                MT_UNROLL for (int t = 0; t < kStage; t++) {
+                    MT_UNROLL for (int r = 0; r < R; r++) {
+                        const int i = row(r);
+                        const bool below = i > j0 + t && i < n && j0 + t < n;
+                        const double v = M[below ? (int)__umul24((unsigned)i, (unsigned)ld) + j0 + t : 0];
+                        Q[(t * R + r) * 64 + lane] = below ? v : 0.0;
+                    }
+                }
+                MT_UNROLL for (int t = 0; t < kStage; t++) {
+                    if (j0 + t >= n) break;
+                    const double yj = owner_scaled(b, j0 + t);
+                    MT_UNROLL for (int r = 0; r < R; r++) b[r] = fma(-Q[(t * R + r) * 64 + lane], yj, b[r]);
+                }
+            }
+        } else {
+            for (int j = 0; j < n; j++) {
+                const double yj = owner_scaled(b, j);
+                MT_UNROLL for (int r = 0; r < R; r++) {
+                    const int i = row(r);
+                    const bool below = i > j && i < n;
+                    const double l = M[below ? (int)__umul24((unsigned)i, (unsigned)ld) + j : 0];
+                    b[r] = fma(-(below ? l : 0.0), yj, b[r]);
+                }
             }
         }
         MT_UNROLL for (int r = 0; r < R; r++) b[r] = valid(r) ? b[r] * dinv[r] : b[r];
@@ -683,13 +707,31 @@ struct WaveTron {
     // L^T y = b in place, the same way
     MT_INLINE void bwd(double (&b)[R]) const
     {
-        for (int j = n - 1; j >= 0; j--) {
-            const double yj = owner_scaled(b, j);
-            MT_UNROLL for (int r = 0; r < R; r++) {
-                const int i = row(r);
-                const bool above = i < j;
-                const double l = M[above ? (int)__umul24((unsigned)j, (unsigned)ld) + i : 0];
-                b[r] = fma(-(above ? l : 0.0), yj, b[r]);
+        if constexpr (kGlobal) {
+            for (int j0 = ((n - 1) / kStage) * kStage; j0 >= 0; j0 -= kStage) {
+                MT_UNROLL for (int t = 0; t < kStage; t++) {
+                    MT_UNROLL for (int r = 0; r < R; r++) {
+                        const int i = row(r);
+                        const bool above = i < j0 + t && j0 + t < n;
+                        const double v = M[above ? (int)__umul24((unsigned)(j0 + t), (unsigned)ld) + i : 0];
+                        Q[(t * R + r) * 64 + lane] = above ? v : 0.0;
+                    }
+                }
+                MT_UNROLL for (int t = kStage - 1; t >= 0; t--) {
+                    if (j0 + t >= n) continue;
+                    const double yj = owner_scaled(b, j0 + t);
+                    MT_UNROLL for (int r = 0; r < R; r++) b[r] = fma(-Q[(t * R + r) * 64 + lane], yj, b[r]);
+                }
+            }
+        } else {
+            for (int j = n - 1; j >= 0; j--) {
+                const double yj = owner_scaled(b, j);
+                MT_UNROLL for (int r = 0; r < R; r++) {
+                    const int i = row(r);
+                    const bool above = i < j;
+                    const double l = M[above ? (int)__umul24((unsigned)j, (unsigned)ld) + i : 0];
+                    b[r] = fma(-(above ? l : 0.0), yj, b[r]);
+                }
             }
         }
         MT_UNROLL for (int r = 0; r < R; r++) b[r] = valid(r) ? b[r] * dinv[r] : b[r];
