@@ -595,6 +595,20 @@ struct WaveTron {
                 // rows past n read row 0 (always present) and use 0
                 const bool ain = ka < n, bin = jb < n;
                 int q0 = 0;
+                if constexpr (kGlobal) {
+                    // operands from L2: eight chunks' loads in flight per round trip
+                    for (; q0 + 32 <= j0; q0 += 32) {
+                        double av[8], bv[8];
+                        MT_UNROLL for (int u = 0; u < 8; u++) {
+                            av[u] = ra[q0 + 4 * u];
+                            bv[u] = rb[q0 + 4 * u];
+                        }
+                        MT_UNROLL for (int u = 0; u < 8; u += 2) {
+                            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ain ? -av[u] : 0.0, bin ? bv[u] : 0.0, acc0, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ain ? -av[u + 1] : 0.0, bin ? bv[u + 1] : 0.0, acc1, 0, 0, 0);
+                        }
+                    }
+                }
                 for (; q0 + 8 <= j0; q0 += 8) {
                     const double a0 = ra[q0], b0 = rb[q0], a1 = ra[q0 + 4], b1 = rb[q0 + 4];
                     acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ain ? -a0 : 0.0, bin ? b0 : 0.0, acc0, 0, 0, 0);
