@@ -125,7 +125,7 @@ typedef struct {
     int32_t lane_block;   /* 64 or 256 */
 } tron_plan_spec;
 
-/* lane_max_n 8, edges 16/32/64/128, 4 streams, lane_block 256. */
+/* lane_max_n 8, edges 16/24/32/40/48/56/64/80/96/112/128, 4 streams, lane_block 64. */
 void tron_default_plan_spec(tron_plan_spec *spec);
 /* tron_batch_create with an explicit plan (spec NULL = default). INVALID for a bad spec,
  * UNSUPPORTED when some n exceeds the largest edge. */

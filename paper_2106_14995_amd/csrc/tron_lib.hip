@@ -380,14 +380,19 @@ static void launch_bucket(tron_family fam, const Bucket &b, const LaneArgs &a0, 
     launch_wave_fam(fam, a, b.nmax, st);
 }
 
+// The default plan: the autotuner's usual choice on large uneven batches. Edges every 8 up to
+// 64 keep each bucket's LDS request (n_max ((n_max+1)|1) x 8 B) close to what its instances
+// need, so smaller instances are not held to the residency of the largest; 64-lane
+// workgroups spread the lane kernels' few thousand lanes over more CUs.
 static void default_spec(tron_plan_spec *p)
 {
+    constexpr int kN = 11;
+    const int e[kN] = {16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128};
     p->lane_max_n = 8;
-    p->nedges = 4;
-    const int e[4] = {16, 32, 64, 128};
-    for (int i = 0; i < 16; i++) p->edges[i] = i < 4 ? e[i] : 0;
+    p->nedges = kN;
+    for (int i = 0; i < 16; i++) p->edges[i] = i < kN ? e[i] : 0;
     p->streams = kMaxSideStreams;
-    p->lane_block = 256;
+    p->lane_block = 64;
 }
 
 static tron_err check_spec(const tron_plan_spec &p)

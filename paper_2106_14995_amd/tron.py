@@ -424,7 +424,11 @@ class Server:
             pass
 
 
-def plan_spec(lane_max_n=8, edges=(16, 32, 64, 128), streams=4, lane_block=256) -> PlanSpec:
+DEFAULT_EDGES = (16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128)
+
+
+def plan_spec(lane_max_n=8, edges=DEFAULT_EDGES, streams=4, lane_block=64) -> PlanSpec:
+    """A bucket plan (the defaults are the library's default plan)."""
     p = PlanSpec()
     p.lane_max_n, p.nedges, p.streams, p.lane_block = lane_max_n, len(edges), streams, lane_block
     for i, e in enumerate(edges):

@@ -48,6 +48,16 @@ def test_host_helpers():
     assert (a.ctol, a.outer_max, a.rho_growth, a.decrease, a.rho_max) == (1e-6, 50, 10.0, 0.25, 1e6)
 
 
+def test_default_plan_spec_matches_the_binding():
+    from paper_2106_14995_amd import tron
+    spec = tron.PlanSpec()
+    tron.lib().tron_default_plan_spec(C.byref(spec))
+    mine = tron.plan_spec()
+    assert spec.lane_max_n == mine.lane_max_n and spec.streams == mine.streams
+    assert spec.lane_block == mine.lane_block == 64
+    assert list(spec.edges[:spec.nedges]) == list(tron.DEFAULT_EDGES) == list(mine.edges[:mine.nedges])
+
+
 def test_design_calls_reject_bad_arguments_before_touching_the_device():
     from paper_2106_14995_amd import tron
     L = tron.lib()
