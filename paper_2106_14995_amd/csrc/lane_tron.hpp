@@ -58,6 +58,17 @@ MT_INLINE double clampf(double v, double lo, double hi) { return fmin(fmax(v, lo
 MT_INLINE double dmax(double a, double b) { return a > b ? a : b; }
 MT_INLINE double dmin(double a, double b) { return a < b ? a : b; }
 
+// 1/sqrt(d) for a positive finite d: the hardware estimate y (about single precision) and
+// one third-order correction from the binomial series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ...
+// with e = 1 - d y^2, which leaves a relative error of order e^3. Four dependent operations
+// after the estimate; a pivot of the factorisation is on a serial chain, so this matters.
+MT_INLINE double rsqrt_pos(double d)
+{
+    const double y = __builtin_amdgcn_rsq(d);
+    const double e = fma(-(d * y), y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+
 // projected-gradient component (section 5.1): g inside, min(g,0) at l, max(g,0) at u, 0 if
 // l = u; g is finite wherever this is called (finiteness is checked first)
 MT_INLINE double pg_comp(double x, double lo, double hi, double g)
@@ -557,7 +568,7 @@ struct LaneTron {
             double d = fam.H(j, j) + alpha;
             MT_UNROLL for (int k = 0; k < j; k++) d = fma(-L[tri(j, k)], L[tri(j, k)], d);
             ok = ok && (!fj || d > 0.0);
-            const double r = fj ? rsqrt(d) : 1.0;  // 1 / pivot
+            const double r = fj ? rsqrt_pos(d) : 1.0;  // 1 / pivot
             L[tri(j, j)] = fj ? d * r : 1.0;        // pivot = d / sqrt(d)
             dinv[j] = r;
             MT_UNROLL for (int i = j + 1; i < N; i++) {

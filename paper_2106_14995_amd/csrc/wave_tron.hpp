@@ -65,17 +65,6 @@ MT_INLINE double bcast(double v, int src)
     return __hiloint2double(hi, lo);
 }
 
-// 1/sqrt(d) for a positive finite d: the hardware estimate y (about single precision) and
-// one third-order correction from the binomial series (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ...
-// with e = 1 - d y^2, which leaves a relative error of order e^3. Four dependent operations
-// after the estimate; a pivot of the factorisation is on a serial chain, so this matters.
-MT_INLINE double rsqrt_pos(double d)
-{
-    const double y = __builtin_amdgcn_rsq(d);
-    const double e = fma(-(d * y), y, 1.0);
-    return fma(y * e, fma(e, 0.375, 0.5), y);
-}
-
 MT_INLINE double max_nan(double a, double b) { return (b > a || b != b) ? b : a; }  // NaN propagates
 
 MT_INLINE double wave_max(double v)
