@@ -470,16 +470,25 @@ def main():
     n_conv = int((st == 0).sum().item())
     log(f"converged {n_conv}/{B}; iters p50 {int(it.median().item())} max {int(it.max().item())}")
 
+    # throughput: K back-to-back solves between two device synchronisations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        h.solve(params, lo, hi, x0, x, f, st, it, stream=stream)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+
+    # latency: K more solves, each between its own pair of events on the launch stream (the
+    # event packets add a few microseconds between launches, so this pass is kept out of the
+    # throughput); the mean is the kernel's launch duration for the roofline
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for k in range(args.steps):
         starts[k].record(stream)
         h.solve(params, lo, hi, x0, x, f, st, it, stream=stream)
         ends[k].record(stream)
     torch.cuda.synchronize()
-    total = time.perf_counter() - t0
     lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])  # ms per launch
     log(f"timed {args.steps} steps in {total:.3f} s; launch ms p50 {np.median(lat):.4f}")
 
