@@ -470,17 +470,21 @@ def main():
     n_conv = int((st == 0).sum().item())
     log(f"converged {n_conv}/{B}; iters p50 {int(it.median().item())} max {int(it.max().item())}")
 
-    # throughput: K back-to-back solves between two device synchronisations
+    # throughput: K back-to-back solves between two device synchronisations; one pair of
+    # events on the launch stream around them gives the kernel's mean launch duration
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    ev0.record(stream)
     for _ in range(args.steps):
         h.solve(params, lo, hi, x0, x, f, st, it, stream=stream)
+    ev1.record(stream)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
+    launch_ms = ev0.elapsed_time(ev1) / args.steps
 
-    # latency: K more solves, each between its own pair of events on the launch stream (the
-    # event packets add a few microseconds between launches, so this pass is kept out of the
-    # throughput); the mean is the kernel's launch duration for the roofline
+    # latency: K more solves, each between its own pair of events (the event packets add a
+    # few microseconds between launches, so this pass is kept out of the throughput)
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -490,7 +494,8 @@ def main():
         ends[k].record(stream)
     torch.cuda.synchronize()
     lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])  # ms per launch
-    log(f"timed {args.steps} steps in {total:.3f} s; launch ms p50 {np.median(lat):.4f}")
+    log(f"timed {args.steps} steps in {total:.3f} s; launch ms mean {launch_ms:.4f}, "
+        f"bracketed one by one p50 {np.median(lat):.4f}")
 
     # per-instance solve latency from device timestamps (one more solve, outside the timing)
     ts = torch.zeros(2 * B, dtype=torch.int64, device="cuda")
@@ -526,7 +531,7 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cb = cpu_baseline(bt, args.cpu_seconds)
-        kern_s = float(lat.mean()) * 1e-3
+        kern_s = launch_ms * 1e-3
         flops = cb["flops_per_instance"] * B
         bytes_ = BR6_BYTES * B
         t_flop, t_byte = flops / PEAK_FP64_VECTOR, bytes_ / PEAK_HBM
