@@ -70,20 +70,25 @@ def cpu_baseline(bt, budget_s):
 
 
 def time_solves(solve, steps, warmup, stream):
-    """Run `solve()` warmup + steps times; per-step HIP-event latency (ms) and wall time (s)."""
+    """Run `solve()` warmup times, then `steps` times back to back for the wall time (s), then
+    `steps` more times, each between its own pair of HIP events, for per-step latencies (ms);
+    the event packets add a few microseconds between steps, so they stay out of the wall time."""
     import torch
     for _ in range(warmup):
         solve()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solve()
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    t0 = time.perf_counter()
     for k in range(steps):
         starts[k].record(stream)
         solve()
         ends[k].record(stream)
     torch.cuda.synchronize()
-    total = time.perf_counter() - t0
     return np.array([a.elapsed_time(b) for a, b in zip(starts, ends)]), total
 
 
