@@ -15,6 +15,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "tron_oracle.c")
 _SO = os.path.join(_HERE, "_tron_oracle.so")
+# The planted-mistake check (tests/test_oracle_mutations.py) builds altered copies of the
+# oracle and points this variable at one of them; nothing else sets it.
+_SO_OVERRIDE = os.environ.get("TRON_ORACLE_SO_OVERRIDE")
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=gnu11", "-Wall", "-Wextra",
           "-shared", "-fPIC"]
 
@@ -60,9 +63,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-            build()
-        L = C.CDLL(_SO)
+        if _SO_OVERRIDE:
+            L = C.CDLL(_SO_OVERRIDE)
+        else:
+            if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+                build()
+            L = C.CDLL(_SO)
         P = C.c_void_p
         L.or_param_size.restype = C.c_int64
         L.or_param_size.argtypes = [C.c_int32, C.c_int32]
@@ -86,6 +92,18 @@ def lib():
         L.or_projgrad_inf.argtypes = [C.c_int32, P, P, P, P]
         L.or_subspace_cg.restype = C.c_int32
         L.or_subspace_cg.argtypes = [C.c_int32, P, P, C.c_double, C.c_double, P, P, P, P]
+        L.or_radius_update.restype = C.c_double
+        L.or_radius_update.argtypes = [C.c_double] * 6 + [C.c_int32]
+        L.or_cauchy_step.restype = C.c_double
+        L.or_cauchy_step.argtypes = [C.c_int32, P, P, P, P, P, C.c_double, C.c_double, P, P]
+        L.or_projected_search.restype = C.c_int32
+        L.or_projected_search.argtypes = [C.c_int32, P, P, P, P, P, P, P, P, P]
+        L.or_step_norm.restype = C.c_double
+        L.or_step_norm.argtypes = [C.c_int32, P, C.c_int32, P, P]
+        L.or_actual_reduction.restype = C.c_double
+        L.or_actual_reduction.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, P, P, P]
+        L.or_family_flops.restype = C.c_double
+        L.or_family_flops.argtypes = [C.c_int32, C.c_int32, C.c_int32]
         L.or_al_batch.restype = C.c_int32
         L.or_al_batch.argtypes = [C.c_int64, P, P, P, P, P, P, P, P, P, P, C.POINTER(Opts),
                                   C.POINTER(AlOpts), C.c_int32]
@@ -236,6 +254,49 @@ def subspace_cg(a, r, delta, cg_rtol=0.1):
     it = np.zeros(1, dtype=np.int32); shift = np.zeros(1)
     ex = lib().or_subspace_cg(m, _p(a), _p(r), delta, cg_rtol, _p(w), _p(sh), _p(it), _p(shift))
     return dict(exit=int(ex), w=w, shat=sh, iters=int(it[0]), shift=float(shift[0]))
+
+
+def radius_update(delta, rho, f, ft, gts, snorm, finite=True):
+    return lib().or_radius_update(delta, rho, f, ft, gts, snorm, 1 if finite else 0)
+
+
+def cauchy_step(x, lo, hi, g, H, delta, alpha):
+    """Returns (alpha, xs, trials)."""
+    x, lo, hi, g = map(_f64, (x, lo, hi, g))
+    H = _f64(H)
+    xs = np.zeros_like(x)
+    tr = np.zeros(1, dtype=np.int32)
+    a = lib().or_cauchy_step(x.shape[0], _p(x), _p(lo), _p(hi), _p(g), _p(H), delta, alpha,
+                             _p(xs), _p(tr))
+    return a, xs, int(tr[0])
+
+
+def projected_search(xs, lo, hi, w, r, H):
+    """Returns (accepted, new xs, last beta tried, trials)."""
+    xs, lo, hi, w, r = map(_f64, (xs, lo, hi, w, r))
+    H = _f64(H)
+    out = np.zeros_like(xs)
+    beta = np.zeros(1)
+    tr = np.zeros(1, dtype=np.int32)
+    acc = lib().or_projected_search(xs.shape[0], _p(xs), _p(lo), _p(hi), _p(w), _p(r), _p(H),
+                                    _p(out), _p(beta), _p(tr))
+    return bool(acc), out, float(beta[0]), int(tr[0])
+
+
+def step_norm(s, free_idx, L):
+    s = _f64(s)
+    idx = np.ascontiguousarray(free_idx, dtype=np.int32)
+    L = _f64(L) if len(idx) else np.zeros(1)
+    return lib().or_step_norm(s.shape[0], _p(s), len(idx), _p(idx), _p(L))
+
+
+def actual_reduction(f, ft, pred, g, gt, s):
+    g, gt, s = map(_f64, (g, gt, s))
+    return lib().or_actual_reduction(s.shape[0], f, ft, pred, _p(g), _p(gt), _p(s))
+
+
+def family_flops(family, n, which):
+    return lib().or_family_flops(family, n, which)
 
 
 # ---------------------------------------------------------------- component ADMM

@@ -20,6 +20,12 @@
  *
  * Algorithmic flop counts (the `fl` accumulators) use textbook counts: a multiply or an
  * add is 1, a division 1, a square root 1, a sine or cosine 1; comparisons and copies 0.
+ * Core operations are charged by their textbook formulas (dot 2m, nrm2 2m+1, axpy 2m,
+ * gemv 2m^2, triangular solve m^2, Cholesky column j: 2j+1 for the pivot and 2j+1 per
+ * entry below it, gpstep 3n, breakpt 2 per breakpoint). The evaluations of the QP4 and
+ * BR6 families are charged the minimal counts of the method's own work, each quantity
+ * formed once per point (FAM_FLOPS below), not the loops this file happens to use to
+ * evaluate them; BR8L and HS45M are charged as written.
  */
 #include "tron_oracle.h"
 
@@ -564,28 +570,69 @@ static void hs45_h(int n, const double *x, double *h, double *fl)
         }
 }
 
+/* Minimal algorithmic counts of one evaluation (FAM_FLOPS). The solver evaluates f first
+ * at every point, then the gradient at the same point, and the Hessian only at points
+ * whose f and gradient it has, so the gradient and Hessian counts exclude what the
+ * earlier evaluations at that point already formed.
+ *   QP4  f: Qx 2n^2, x'Qx 2n, c'x 2n, x_i^2 and x_i^4 2n, their sum n, the combination 4
+ *          = 2n^2 + 7n + 4;
+ *        g (Qx and x_i^2 from f): + c n, x_i^3 n, 4 kappa 1, times x_i^3 n, add n = 4n + 1;
+ *        H (Q as given, x_i^2 from f): 12 kappa 1, times x_i^2 n, add to Q_ii n = 2n + 1.
+ *   BR6  shared: th_i - th_j 1, sin and cos 2, v_i v_j 1, v_i^2 and v_j^2 2, per flow
+ *          phi = al cos + be sin 3 and a w_own + V phi 3 (four flows) = 30;
+ *        f: ten residuals 10, ten terms (lambda + (rho/2) e) e 4 each, nine sums = 89;
+ *        g: ten coefficients lambda + rho e 2 each 20, copy couplings folded into the p
+ *          flows 2, dphi/dD 3 per flow 12, two 4-term sums over the flows 14, d/dv_i and
+ *          d/dv_j 8 each 16, d/dth_i and d/dth_j 3 = 67;
+ *        H: flow derivatives in (v_i, v_j, D) 6 per flow 24, Gauss-Newton weights of the
+ *          p flows with their copies 2, per flow the six distinct (v_i, v_j, D) entries
+ *          (weighted products 9, second derivatives 3, curvature terms 5, sums 11) 28 each
+ *          112, the v^2 couplings 5 each 10, the angle couplings 2, the copy rows 6 = 156. */
+static double fam_flops(int fam, int n, int which)
+{
+    if (fam == OR_QP4) {
+        if (which == 0) return 2.0 * n * n + 7.0 * n + 4.0;
+        if (which == 1) return 4.0 * n + 1.0;
+        return 2.0 * n + 1.0;
+    }
+    /* OR_BR6 */
+    if (which == 0) return 89.0;
+    if (which == 1) return 67.0;
+    return 156.0;
+}
+
 static double fam_f(int fam, int n, const double *p, const double *x, double *fl)
 {
-    if (fam == OR_QP4) return qp4_f(n, p, x, fl);
-    if (fam == OR_BR6) return br6_f(p, x, fl);
+    double as_written = 0.0;
+    if (fam == OR_QP4) { double v = qp4_f(n, p, x, &as_written); *fl += fam_flops(fam, n, 0); return v; }
+    if (fam == OR_BR6) { double v = br6_f(p, x, &as_written); *fl += fam_flops(fam, n, 0); return v; }
     if (fam == OR_BR8L) return br8l_f(p, x, fl);
     return hs45_f(n, x, fl);
 }
 
 static void fam_g(int fam, int n, const double *p, const double *x, double *g, double *fl)
 {
-    if (fam == OR_QP4) qp4_g(n, p, x, g, fl);
-    else if (fam == OR_BR6) br6_g(p, x, g, fl);
+    double as_written = 0.0;
+    if (fam == OR_QP4) { qp4_g(n, p, x, g, &as_written); *fl += fam_flops(fam, n, 1); }
+    else if (fam == OR_BR6) { br6_g(p, x, g, &as_written); *fl += fam_flops(fam, n, 1); }
     else if (fam == OR_BR8L) br8l_g(p, x, g, fl);
     else hs45_g(n, x, g, fl);
 }
 
 static void fam_h(int fam, int n, const double *p, const double *x, double *h, double *fl)
 {
-    if (fam == OR_QP4) qp4_h(n, p, x, h, fl);
-    else if (fam == OR_BR6) br6_h(p, x, h, fl);
+    double as_written = 0.0;
+    if (fam == OR_QP4) { qp4_h(n, p, x, h, &as_written); *fl += fam_flops(fam, n, 2); }
+    else if (fam == OR_BR6) { br6_h(p, x, h, &as_written); *fl += fam_flops(fam, n, 2); }
     else if (fam == OR_BR8L) br8l_h(p, x, h, fl);
     else hs45_h(n, x, h, fl);
+}
+
+double or_family_flops(int32_t family, int32_t n, int32_t which)
+{
+    if (family != OR_QP4 && family != OR_BR6) return -1.0;
+    if (which < 0 || which > 2) return -1.0;
+    return fam_flops(family, n, which);
 }
 
 double or_eval_f(int32_t family, int32_t n, const double *params, const double *x)
@@ -753,6 +800,33 @@ static int pcg(ws_t *w, int m, double delta, double cg_rtol)
     return CG_MAXIT;
 }
 
+/* Projected search along w from the subspace point xs (Algorithm 1, projected line search;
+ * reading S13): the first beta in 1, 1/2, ..., 2^-20 with
+ *   q(s + d) - q(s) = r'd + d'Hd/2 <= mu0 r'd,   d = P[xs + beta w] - xs,
+ * where r = g + H s is the model gradient at xs. On acceptance xs moves to P[xs + beta w];
+ * otherwise it stays. Returns 1 on acceptance; *beta_out is the last beta tried. */
+static int projected_search(ws_t *w, double *beta_out)
+{
+    int n = w->n;
+    double beta = 1.0, tried = 1.0;
+    int acc = 0;
+    for (int t = 0; t <= SEARCH_HALVINGS; t++) {
+        w->search_trials++;
+        tried = beta;
+        gpstep_pt(n, w->xs, w->lo, w->hi, beta, w->w, w->xt, w->d, &w->fl);
+        gemv(n, w->H, w->d, w->hv, &w->fl);
+        double rd = dot(n, w->r, w->d, &w->fl);
+        double dq = rd + 0.5 * dot(n, w->d, w->hv, &w->fl);
+        w->fl += 3.0;
+        if (dq <= MU0 * rd) { acc = 1; break; }
+        beta *= 0.5;
+        w->fl += 1.0;
+    }
+    if (acc) memcpy(w->xs, w->xt, sizeof(double) * n);
+    *beta_out = tried;
+    return acc;
+}
+
 /* Subspace passes (Algorithm 1: free set, preconditioner, CG, back-transform, projected
  * search; reading S13). Starts from xs (the Cauchy point) and moves it. */
 static void subspace(ws_t *w, double delta, double cg_rtol)
@@ -769,7 +843,7 @@ static void subspace(ws_t *w, double delta, double cg_rtol)
         for (int i = 0; i < n; i++) w->s[i] = w->xs[i] - w->x[i];
         gemv(n, w->H, w->s, w->r, &w->fl);
         for (int i = 0; i < n; i++) w->r[i] += w->g[i];
-        w->fl += 2.0 * n;
+        w->fl += n;
         for (int a = 0; a < m; a++) {
             w->rF[a] = w->r[w->idx[a]];
             for (int b = 0; b < m; b++) w->A[a * m + b] = w->H[w->idx[a] * n + w->idx[b]];
@@ -782,22 +856,8 @@ static void subspace(ws_t *w, double delta, double cg_rtol)
         trsv_bwd(m, w->L, w->wF, &w->fl);              /* w = L^-T s_hat */
         for (int i = 0; i < n; i++) w->w[i] = 0.0;
         for (int a = 0; a < m; a++) w->w[w->idx[a]] = w->wF[a];
-        /* projected search: first beta in 1, 1/2, ... with
-         * q(s + d) - q(s) = r'd + d'Hd/2 <= mu0 r'd, d = P[xs + beta w] - xs */
-        double beta = 1.0;
-        int acc = 0;
-        for (int t = 0; t <= SEARCH_HALVINGS; t++) {
-            w->search_trials++;
-            gpstep_pt(n, w->xs, w->lo, w->hi, beta, w->w, w->xt, w->d, &w->fl);
-            gemv(n, w->H, w->d, w->hv, &w->fl);
-            double rd = dot(n, w->r, w->d, &w->fl);
-            double dq = rd + 0.5 * dot(n, w->d, w->hv, &w->fl);
-            w->fl += 3.0;
-            if (dq <= MU0 * rd) { acc = 1; break; }
-            beta *= 0.5;
-            w->fl += 1.0;
-        }
-        if (acc) memcpy(w->xs, w->xt, sizeof(double) * n);
+        double beta;
+        projected_search(w, &beta);
         int newly_bound = 0;
         for (int a = 0; a < m; a++) {
             int i = w->idx[a];
@@ -868,6 +928,22 @@ static double radius_update(double delta, double rho, double f, double ft, doubl
     }
     *fl += 3.0;
     return nd;
+}
+
+/* Actual reduction of a trial with finite f(x + s) (reading S30): f - ft, except when the
+ * predicted reduction is at the rounding level of f, pred <= 1e-10 max(1, |f|); the
+ * difference f - ft is then noise and the reduction is taken from the gradients at both
+ * ends, -(g + gt)'s / 2 (the trapezoid rule, exact when f is quadratic along s). */
+static double actual_reduction(int n, double f, double ft, double pred, const double *g,
+                               const double *gt, const double *s, double *fl)
+{
+    if (pred <= ARED_SWITCH * (fabs(f) > 1.0 ? fabs(f) : 1.0)) {
+        double sg = 0.0;
+        for (int i = 0; i < n; i++) sg += (g[i] + gt[i]) * s[i];
+        *fl += 3.0 * n + 1.0;
+        return -0.5 * sg;
+    }
+    return f - ft;
 }
 
 static int all_finite(int n, const double *v)
@@ -946,15 +1022,7 @@ static int tron_one(int fam, int n, const double *prm, const double *lo, const d
         w.fl += 1.0;
         if (fin) {
             fam_g(fam, n, prm, w.xs, w.gt, &w.fl);
-            /* reading S30: when the predicted reduction is at the rounding level of f, the
-             * difference f - ft is noise; take the reduction from the gradients instead,
-             * -(g + gt)'s / 2 (the trapezoid rule, exact when f is quadratic along s) */
-            if (pred <= ARED_SWITCH * (fabs(f) > 1.0 ? fabs(f) : 1.0)) {
-                double sg = 0.0;
-                for (int i = 0; i < n; i++) sg += (w.g[i] + w.gt[i]) * w.s[i];
-                ared = -0.5 * sg;
-                w.fl += 3.0 * n + 1.0;
-            }
+            ared = actual_reduction(n, f, ft, pred, w.g, w.gt, w.s, &w.fl);
         }
         double rho = fin ? ared / pred : -INFINITY;
         w.fl += 1.0;
@@ -1011,6 +1079,81 @@ int32_t or_subspace_cg(int32_t m, const double *a, const double *r, double delta
     *shift_out = shift;
     free(buf);
     return ex;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Single steps of one TRON iteration, exposed for the tests.                            */
+/* ------------------------------------------------------------------------------------ */
+static ws_t step_ws(int n, const double *lo, const double *hi, double *buf)
+{
+    ws_t w;
+    memset(&w, 0, sizeof(w));
+    w.n = n; w.lo = lo; w.hi = hi;
+    double *q = buf;
+    w.x = q; q += n; w.g = q; q += n; w.xs = q; q += n; w.s = q; q += n; w.xt = q; q += n;
+    w.st = q; q += n; w.r = q; q += n; w.w = q; q += n; w.d = q; q += n; w.hv = q; q += n;
+    w.H = q;
+    return w;
+}
+
+double or_radius_update(double delta, double rho, double f, double ft, double gts, double snorm,
+                        int32_t finite_trial)
+{
+    double fl = 0.0;
+    return radius_update(delta, rho, f, ft, gts, snorm, finite_trial, &fl);
+}
+
+double or_cauchy_step(int32_t n, const double *x, const double *lo, const double *hi,
+                      const double *g, const double *h, double delta, double alpha,
+                      double *xs_out, int32_t *trials)
+{
+    double *buf = (double *)calloc((size_t)n * 10 + (size_t)n * n + 1, sizeof(double));
+    ws_t w = step_ws(n, lo, hi, buf);
+    memcpy(w.x, x, sizeof(double) * n);
+    memcpy(w.g, g, sizeof(double) * n);
+    memcpy(w.H, h, sizeof(double) * n * n);
+    double a = cauchy_step(&w, delta, alpha);
+    memcpy(xs_out, w.xs, sizeof(double) * n);
+    *trials = w.cauchy_trials;
+    free(buf);
+    return a;
+}
+
+int32_t or_projected_search(int32_t n, const double *xs, const double *lo, const double *hi,
+                            const double *dir, const double *r, const double *h,
+                            double *xs_out, double *beta_out, int32_t *trials)
+{
+    double *buf = (double *)calloc((size_t)n * 10 + (size_t)n * n + 1, sizeof(double));
+    ws_t w = step_ws(n, lo, hi, buf);
+    memcpy(w.xs, xs, sizeof(double) * n);
+    memcpy(w.w, dir, sizeof(double) * n);
+    memcpy(w.r, r, sizeof(double) * n);
+    memcpy(w.H, h, sizeof(double) * n * n);
+    int acc = projected_search(&w, beta_out);
+    memcpy(xs_out, w.xs, sizeof(double) * n);
+    *trials = w.search_trials;
+    free(buf);
+    return acc;
+}
+
+double or_step_norm(int32_t n, const double *s, int32_t m, const int32_t *free_idx,
+                    const double *l)
+{
+    ws_t w;
+    memset(&w, 0, sizeof(w));
+    int *idx = (int *)calloc((size_t)(m > 0 ? m : 1), sizeof(int));
+    for (int a = 0; a < m; a++) idx[a] = free_idx[a];
+    w.n = n; w.lm = m; w.lidx = idx; w.L = (double *)l; w.s = (double *)s;
+    double v = step_norm(&w);
+    free(idx);
+    return v;
+}
+
+double or_actual_reduction(int32_t n, double f, double ft, double pred, const double *g,
+                           const double *gt, const double *s)
+{
+    double fl = 0.0;
+    return actual_reduction(n, f, ft, pred, g, gt, s, &fl);
 }
 
 /* ------------------------------------------------------------------------------------ */

@@ -40,7 +40,7 @@ typedef struct {
 int64_t or_param_size(int32_t family, int32_t n);
 
 /* Per-instance statistics written by or_tron_batch when stats != NULL, OR_NSTAT doubles each:
- * [0] algorithmic flops, [1] outer iterations, [2] CG iterations, [3] Cholesky attempts,
+ * [0] algorithmic flops (textbook counts; minimal family counts for QP4 and BR6), [1] outer iterations, [2] CG iterations, [3] Cholesky attempts,
  * [4] Cauchy trials, [5] projected-search trials, [6] subspace passes, [7] accepted steps. */
 #define OR_NSTAT 8
 
@@ -78,6 +78,35 @@ double or_projgrad_inf(int32_t n, const double *x, const double *lo, const doubl
  * 2 negative curvature, 3 trust boundary); w receives L^{-T} s_hat, *iters the count. */
 int32_t or_subspace_cg(int32_t m, const double *a, const double *r, double delta, double cg_rtol,
                        double *w, double *shat, int32_t *iters, double *shift_out);
+
+/* Single steps of one iteration (Algorithm 1 and the readings of section 3), for the tests.
+ * or_radius_update: the new radius after a trial with ratio rho (reading S2); ft is f at
+ *   the trial point, gts = g's, snorm the step length in the norm of reading S31.
+ * or_cauchy_step: the Cauchy search from alpha (reading S4) on the model with gradient g
+ *   and dense row-major Hessian h at x; returns the accepted alpha, writes P[x - alpha g]
+ *   to xs_out and the number of trial points to *trials.
+ * or_projected_search: the search along dir from xs with model gradient r = g + Hs at xs
+ *   (reading S13); returns 1 when a step was accepted, writes the new xs, the last beta
+ *   tried and the number of trials.
+ * or_step_norm: ||L^T s_F|| on the m free indices free_idx (L the m x m row-major factor of
+ *   that block), combined with ||s|| on the other indices (reading S31); m = 0 gives ||s||.
+ * or_actual_reduction: f - ft, or -(g + gt)'s / 2 when pred is at the rounding level of f
+ *   (reading S30).
+ * or_family_flops: the minimal count charged for one evaluation (which = 0 f, 1 gradient
+ *   after f at the same point, 2 Hessian after both) of QP4 or BR6; -1 otherwise. */
+double or_radius_update(double delta, double rho, double f, double ft, double gts, double snorm,
+                        int32_t finite_trial);
+double or_cauchy_step(int32_t n, const double *x, const double *lo, const double *hi,
+                      const double *g, const double *h, double delta, double alpha,
+                      double *xs_out, int32_t *trials);
+int32_t or_projected_search(int32_t n, const double *xs, const double *lo, const double *hi,
+                            const double *dir, const double *r, const double *h,
+                            double *xs_out, double *beta_out, int32_t *trials);
+double or_step_norm(int32_t n, const double *s, int32_t m, const int32_t *free_idx,
+                    const double *l);
+double or_actual_reduction(int32_t n, double f, double ft, double pred, const double *g,
+                           const double *gt, const double *s);
+double or_family_flops(int32_t family, int32_t n, int32_t which);
 
 /* ---------------- augmented-Lagrangian loop (section 1) for BR8L instances ---------------- */
 typedef struct {

@@ -1,0 +1,325 @@
+"""Pins of the oracle's single steps: the readings the paper leaves to the TRON method it
+cites (section 3), each checked on hand-worked cases whose expected values follow from the
+reading by hand, not from the oracle.
+
+* S2  radius update: every interval of the ratio, the ties at eta0, eta1 and eta2, both
+      branches of the step-length factor alpha* (gamma <= 0 and gamma > 0, clipped or not),
+      and a non-finite trial.
+* S4  Cauchy search: extrapolation stopped by the largest breakpoint, interpolation forced
+      by the trust region, and a start whose acceptance is decided by the sufficient-
+      decrease constant mu0.
+* S13 projected search: a full step shortened by a bound, halving to the first acceptable
+      beta (again decided by mu0), an uphill direction with no acceptable beta, and a
+      direction blocked at the bound.
+* S31 step norm: ||L^T s_F|| combined with ||s|| off the free set, against NumPy.
+* S30 the rounding-level switch of the actual reduction, just above and below
+      1e-10 max(1, |f|).
+* The flop counter: two whole solves of one-variable box QPs traced by hand, operation by
+  operation, with the textbook counts; and the first evaluation of each family.
+"""
+import math
+
+import numpy as np
+import pytest
+
+INF = math.inf
+
+# ------------------------------------------------------------------ S2 radius update
+# delta = 1 throughout; f = 0 and g's = -1, so gamma = ft - f - g's = ft + 1.
+#   ft = -1.5: gamma = -0.5 <= 0            -> alpha* = sigma3 = 4
+#   ft = -0.5: gamma =  0.5, -g's/(2 gamma) = 1    -> alpha* = 1
+#   ft =  2.0: gamma =  3,   -g's/(2 gamma) = 1/6  -> alpha* = max(sigma1, 1/6) = 0.25
+# New radius by interval (sigma1 = 0.25, sigma2 = 0.5, sigma3 = 4):
+#   rho <= eta0          min(max(alpha*, sigma1) ||s||, sigma2 delta)
+#   eta0 < rho <= eta1   max(sigma1 delta, min(alpha* ||s||, sigma2 delta))
+#   eta1 < rho <  eta2   max(sigma1 delta, min(alpha* ||s||, sigma3 delta))
+#   rho >= eta2          max(delta, min(alpha* ||s||, sigma3 delta))
+RADIUS_CASES = [
+    # (ft, ||s||, rho, expected)
+    # alpha* = 4, ||s|| = 0.1 (alpha* ||s|| = 0.4)
+    (-1.5, 0.1, -1.0, 0.4),
+    (-1.5, 0.1, 0.1, 0.4),
+    (-1.5, 0.1, 0.5, 0.4),
+    (-1.5, 0.1, 0.75, 1.0),    # tie at eta2: the expanding interval
+    (-1.5, 0.1, 2.0, 1.0),
+    # alpha* = 4, ||s|| = 10 (alpha* ||s|| = 40)
+    (-1.5, 10.0, -1.0, 0.5),
+    (-1.5, 10.0, 0.1, 0.5),
+    (-1.5, 10.0, 0.25, 0.5),   # tie at eta1: still the shrinking interval
+    (-1.5, 10.0, 0.5, 4.0),
+    (-1.5, 10.0, 0.9, 4.0),
+    # alpha* = 1, ||s|| = 0.1
+    (-0.5, 0.1, -1.0, 0.1),
+    (-0.5, 0.1, 1e-4, 0.1),    # tie at eta0: rejected, first interval
+    (-0.5, 0.1, 0.2, 0.25),
+    (-0.5, 0.1, 0.5, 0.25),
+    (-0.5, 0.1, 0.75, 1.0),    # tie at eta2
+    # alpha* = 1, ||s|| = 3 (alpha* ||s|| = 3)
+    (-0.5, 3.0, 0.5, 3.0),
+    (-0.5, 3.0, 0.8, 3.0),
+    (-0.5, 3.0, 0.1, 0.5),
+    # alpha* clipped to 0.25, ||s|| = 0.1 and 2
+    (2.0, 0.1, -1.0, 0.025),
+    (2.0, 0.1, 0.5, 0.25),
+    (2.0, 2.0, -1.0, 0.5),
+    (2.0, 2.0, 0.8, 1.0),
+]
+
+
+@pytest.mark.parametrize("ft,snorm,rho,expected", RADIUS_CASES)
+def test_radius_update_interval_rule(orc, ft, snorm, rho, expected):
+    got = orc.radius_update(1.0, rho, 0.0, ft, -1.0, snorm)
+    assert got == pytest.approx(expected, rel=1e-15, abs=0.0)
+
+
+def test_radius_update_nonfinite_trial(orc):
+    # a non-finite trial counts as rho = -inf with alpha* = sigma1: min(0.25 ||s||, 0.5 delta)
+    assert orc.radius_update(1.0, 0.0, 0.0, math.nan, -1.0, 0.1, finite=False) == pytest.approx(0.025)
+    assert orc.radius_update(2.0, 5.0, 0.0, math.inf, -1.0, 10.0, finite=False) == pytest.approx(1.0)
+
+
+# ------------------------------------------------------------------ S4 Cauchy search
+def test_cauchy_extrapolation_stops_at_largest_breakpoint(orc):
+    """H = 0, g = (1, 2), x = 0, l = -0.5: breakpoints along -g at 0.5 and 0.25, so the
+    largest is 0.5. alpha = 1e-3 is acceptable (linear model, every trial decreases it by
+    more than mu0 g's) and is multiplied by 10 while below 0.5: 1e-2, 1e-1, 1 are tried and
+    accepted; at alpha = 1 >= 0.5 the search stops. 4 trials; the point is the corner."""
+    x = np.zeros(2)
+    lo = np.array([-0.5, -0.5]); hi = np.array([10.0, 10.0])
+    g = np.array([1.0, 2.0])
+    a, xs, tr = orc.cauchy_step(x, lo, hi, g, np.zeros((2, 2)), 10.0, 1e-3)
+    assert a == pytest.approx(1.0, rel=1e-14)
+    assert np.array_equal(xs, np.array([-0.5, -0.5]))
+    assert tr == 4
+
+
+def test_cauchy_interpolation_on_trust_region(orc):
+    """H = I, g = (3, 4), no bounds, delta = 0.6: alpha = 1 gives ||s|| = 5 > 0.6; alpha =
+    0.1 gives ||s|| = 0.5 and q = -2.5 + 0.125 <= 0.01 (-2.5), accepted after 2 trials."""
+    x = np.zeros(2)
+    lo = np.full(2, -INF); hi = np.full(2, INF)
+    g = np.array([3.0, 4.0])
+    a, xs, tr = orc.cauchy_step(x, lo, hi, g, np.eye(2), 0.6, 1.0)
+    assert a == pytest.approx(0.1, rel=1e-15)
+    assert np.allclose(xs, [-0.3, -0.4], rtol=1e-15)
+    assert tr == 2
+
+
+def test_cauchy_sufficient_decrease_constant(orc):
+    """H = 100 I, g = (3, 4), no bounds, delta = 10, start alpha = 0.019: g's = -0.475,
+    s'Hs/2 = 0.45125, q = -0.02375 <= mu0 g's = -0.00475, acceptable; no finite breakpoint,
+    so alpha = 0.19 is tried (q = -4.75 + 45.125 > 0, rejected): alpha = 0.019, 2 trials.
+    (With mu0 = 0.1 the start would be rejected.)"""
+    x = np.zeros(2)
+    lo = np.full(2, -INF); hi = np.full(2, INF)
+    g = np.array([3.0, 4.0])
+    a, xs, tr = orc.cauchy_step(x, lo, hi, g, 100.0 * np.eye(2), 10.0, 0.019)
+    assert a == 0.019
+    assert tr == 2
+    assert np.allclose(xs, [-0.057, -0.076], rtol=1e-14)
+
+
+def test_cauchy_keeps_last_acceptable_point(orc):
+    """H = I, g = (3, 4), no bounds, delta = 8, start 0.1: 0.1 (||s|| = 0.5) and 1
+    (||s|| = 5, q = -12.5) are acceptable, 10 is not (||s|| = 50): alpha = 1, 3 trials, and
+    the point is that of alpha = 1, not of the rejected trial."""
+    x = np.array([1.0, -1.0])
+    lo = np.full(2, -INF); hi = np.full(2, INF)
+    g = np.array([3.0, 4.0])
+    a, xs, tr = orc.cauchy_step(x, lo, hi, g, np.eye(2), 8.0, 0.1)
+    assert a == pytest.approx(1.0, rel=1e-15)
+    assert tr == 3
+    assert np.allclose(xs, [-2.0, -5.0], rtol=1e-15)
+
+
+# ------------------------------------------------------------------ S13 projected search
+def test_search_full_step_cut_by_bound(orc):
+    """xs = 0, u = 1, w = 3, r = -1, H = 1: beta = 1 projects to 1, d = 1,
+    r d + d H d / 2 = -0.5 <= -0.01: accepted at once."""
+    acc, xs, beta, tr = orc.projected_search(np.zeros(1), np.array([-5.0]), np.array([1.0]),
+                                             np.array([3.0]), np.array([-1.0]), np.eye(1))
+    assert acc and beta == 1.0 and tr == 1 and xs[0] == 1.0
+
+
+def test_search_halving_first_acceptable_beta(orc):
+    """No active bound, r = -1, H = 1, w = 3.8: with d = beta w the test
+    -beta w + (beta w)^2 / 2 <= -mu0 beta w holds iff beta <= 2 (1 - mu0) / w = 0.5211:
+    beta = 1 fails, beta = 1/2 is accepted (with mu0 = 0.1 the bound would be 0.4737)."""
+    acc, xs, beta, tr = orc.projected_search(np.zeros(1), np.array([-100.0]), np.array([100.0]),
+                                             np.array([3.8]), np.array([-1.0]), np.eye(1))
+    assert acc and beta == 0.5 and tr == 2
+    assert xs[0] == pytest.approx(1.9, rel=1e-15)
+
+
+def test_search_two_variables_with_clipping(orc):
+    """xs = 0, u = (0.5, 1), w = (1, 1), r = (-1, -1), H = [[2,1],[1,2]]:
+    beta = 1: d = (0.5, 1), r'd = -1.5, d'Hd = 3.5, change 0.25 > -0.015: rejected;
+    beta = 1/2: d = (0.5, 0.5), r'd = -1, d'Hd = 1.5, change -0.25 <= -0.01: accepted."""
+    H = np.array([[2.0, 1.0], [1.0, 2.0]])
+    acc, xs, beta, tr = orc.projected_search(np.zeros(2), np.array([-1.0, -1.0]),
+                                             np.array([0.5, 1.0]), np.array([1.0, 1.0]),
+                                             np.array([-1.0, -1.0]), H)
+    assert acc and beta == 0.5 and tr == 2
+    assert np.array_equal(xs, np.array([0.5, 0.5]))
+
+
+def test_search_uphill_direction_never_accepts(orc):
+    """r = 1, w = 1, H = 1: the change beta + beta^2/2 exceeds 0.01 beta for every beta > 0,
+    so all 21 values 1, 1/2, ..., 2^-20 are rejected and xs does not move."""
+    acc, xs, beta, tr = orc.projected_search(np.array([0.25]), np.array([-100.0]), np.array([100.0]),
+                                             np.array([1.0]), np.array([1.0]), np.eye(1))
+    assert not acc and tr == 21 and beta == 2.0 ** -20 and xs[0] == 0.25
+
+
+def test_search_blocked_at_bound(orc):
+    """xs at its upper bound and w pointing out of the box: d = 0 and the change 0 <= 0,
+    accepted at beta = 1 without a move."""
+    acc, xs, beta, tr = orc.projected_search(np.array([1.0]), np.array([0.0]), np.array([1.0]),
+                                             np.array([2.0]), np.array([-1.0]), np.eye(1))
+    assert acc and beta == 1.0 and tr == 1 and xs[0] == 1.0
+
+
+# ------------------------------------------------------------------ S31 step norm
+def test_step_norm_uses_transposed_factor(orc):
+    rng = np.random.default_rng(31)
+    n, free = 6, [0, 2, 3, 5]
+    m = len(free)
+    L = np.tril(rng.uniform(0.5, 2.0, (m, m)))
+    s = rng.standard_normal(n)
+    expected = math.sqrt(np.sum((L.T @ s[free]) ** 2) + s[1] ** 2 + s[4] ** 2)
+    assert orc.step_norm(s, free, L) == pytest.approx(expected, rel=1e-14)
+    # L s_F instead of L^T s_F would differ
+    wrong = math.sqrt(np.sum((L @ s[free]) ** 2) + s[1] ** 2 + s[4] ** 2)
+    assert abs(wrong - expected) > 1e-3
+    # no factored pass: the Euclidean norm
+    assert orc.step_norm(s, [], None) == pytest.approx(np.linalg.norm(s), rel=1e-15)
+
+
+# ------------------------------------------------------------------ S30 rounding-level switch
+# g + gt = (1, 0) and s = (1, 2): the trapezoid estimate -(g + gt)'s / 2 = -0.5, while
+# f - ft = f - (f - 1) = 1. The switch is at pred <= 1e-10 max(1, |f|).
+@pytest.mark.parametrize("f,pred,expected", [
+    (2.0, 2.1e-10, 1.0), (2.0, 2.0e-10, -0.5), (2.0, 1.9e-10, -0.5),
+    (0.5, 1.5e-10, 1.0), (0.5, 0.9e-10, -0.5),   # |f| < 1: the threshold is 1e-10
+    (-3.0, 3.1e-10, 1.0), (-3.0, 2.9e-10, -0.5),
+])
+def test_actual_reduction_switch(orc, f, pred, expected):
+    g = np.array([0.25, -0.5]); gt = np.array([0.75, 0.5]); s = np.array([1.0, 2.0])
+    assert orc.actual_reduction(f, f - 1.0, pred, g, gt, s) == expected
+
+
+# ------------------------------------------------------------------ flop counter
+class _One:
+    """One instance of QP4 with n = 1 and kappa = 0: f = q x^2 / 2 + c x."""
+
+    def __init__(self, q, c, lo, hi, x0):
+        self.family = 0
+        self.n = np.array([1], dtype=np.int32)
+        self.params = np.array([q, c, 0.0])
+        self.lo, self.hi, self.x0 = np.array([lo]), np.array([hi]), np.array([x0])
+
+
+def test_flops_hand_ledger_one_iteration(orc):
+    """q = 1, c = -1 on [-10, 10] from x0 = 0 (cold radius 1). Counts per operation with
+    n = m = 1: f 2n^2+7n+4 = 13, gradient 4n+1 = 5, Hessian 2n+1 = 3, gemv 2, dot 2,
+    nrm2 3, gpstep 3, triangular solve 1, Cholesky 2, breakpoint 2.
+      start: f 13, g 5, ||proj grad|| 3, H 3                                    = 24
+      Cauchy: breakpoint 2; trial alpha=1 (gpstep 3, nrm2 3, gemv 2, dots 4,
+              q 3) 15; alpha*10 1; trial 10 fails the radius (gpstep, nrm2) 6   = 24
+      pass: gemv 2, r+g 1, shift rule 2, Cholesky 2, CG (forward solve 1,
+              dot 2, tolerance 2; r = 0 ends it) 5, back-transform 1,
+              search (gpstep 3, gemv 2, dots 4, change 3) 12                    = 25
+      s 1, step norm m(m+1)+2n+1 = 5, model (gemv 2, dots 4, 2) 8, f(xs) 13,
+      f - ft 1, g(xs) 5, ratio 1, radius (gamma 2, alpha* 2, rule 3) 7          = 41
+    total 114; 1 iteration, 1 Cholesky, 2 Cauchy trials, 1 search trial."""
+    r = orc.solve(_One(1.0, -1.0, -10.0, 10.0, 0.0), nthreads=1)
+    st = r["stats"][0]
+    assert r["status"][0] == 0 and r["x"][0] == 1.0
+    assert list(st[1:]) == [1, 0, 1, 2, 1, 1, 1]
+    assert st[0] == 114
+
+
+def test_flops_hand_ledger_boundary_and_interpolation(orc):
+    """q = 1, c = -10 on [-100, 100] from x0 = 0 with delta0 = 2.
+      start: f 13, g 5, H 3                                                     = 21
+      iteration 1 (alpha_c = 1):
+        Cauchy: breakpoint 2; trial 1 fails the radius 6; alpha/10 1; trial 0.1
+                accepted 15                                                     = 24
+        pass: gemv 2, r+g 1, shift 2, Cholesky 2; CG: forward 1, dot 2, tol 2,
+              then one iteration (back 1, gemv 2, forward 1, dot 2, a 1, axpy 2,
+              nrm2 3 -> 9 >= 2: trqsol 3 dots + 9 = 15, axpy 2) 29;
+              back-transform 1; search accepted at beta = 1: 12                 = 54
+        s 1, step norm 5, model 8, f 13, f-ft 1, g 5, ratio 1, radius 7,
+        H at the accepted point 3                                               = 44
+      iteration 2 (alpha_c = 0.1, x = 3, delta = 8):
+        Cauchy: breakpoint 2; trial 0.1 accepted 15; *10 1; trial 1 accepted 15;
+                *10 1; trial 10 fails the radius 6                              = 40
+        pass (r = 0): 2 + 1 + 2 + 2 + 5 + 1 + 12                                = 25
+        s 1, step norm 5, model 8, f 13, f-ft 1, g 5, ratio 1, radius 7         = 41
+    total 249."""
+    r = orc.solve(_One(1.0, -10.0, -100.0, 100.0, 0.0), delta0=2.0, nthreads=1)
+    st = r["stats"][0]
+    assert r["status"][0] == 0 and r["x"][0] == 10.0
+    # iterations, CG iterations, Cholesky attempts, Cauchy trials, search trials, passes,
+    # accepted steps
+    assert list(st[1:]) == [2, 1, 2, 5, 2, 2, 2]
+    assert r["delta"][0] == 8.0
+    assert st[0] == 249
+
+
+def test_flops_first_evaluation_per_family(orc):
+    """A start that already meets gtol costs exactly one f and one gradient: QP4 at
+    n = 8 is (2n^2 + 7n + 4) + (4n + 1) = 221; BR6 is 89 + 67 = 156 (the counts of the
+    minimal evaluation, section 6 of the design notes: shared terms 30, residuals 10,
+    terms 49; coefficients 20, folds 2, angle derivatives 12, sums 14, voltage rows 16,
+    angle rows 3)."""
+    from paper_2106_14995_amd import workloads as W
+    bt = W.br6_zero_residual(4)
+    bt.x0 = bt.xstar.copy()
+    r = orc.solve(bt, gtol=1e-6, nthreads=1)
+    assert np.all(r["iters"] == 0) and np.all(r["stats"][:, 0] == 156)
+    assert orc.family_flops(1, 6, 0) == 89 and orc.family_flops(1, 6, 1) == 67
+    assert orc.family_flops(1, 6, 2) == 156
+    assert orc.family_flops(0, 8, 0) == 188 and orc.family_flops(0, 8, 1) == 33
+    assert orc.family_flops(0, 8, 2) == 17
+
+
+# ------------------------------------------------------------------ CG exits (S5-S10)
+def test_cg_negative_curvature_exit_by_hand(orc):
+    """A = diag(-1, 2), r = (1, 0), delta = 1. Shift rule (S7): min A_ii = -1, so
+    beta = 1e-3 max(1, 2) = 2e-3 and alpha = beta + 1 = 1.002; L = diag(sqrt(0.002),
+    sqrt(3.002)). The first direction is p = -L^-1 r = (-1/sqrt(0.002), 0) and
+    p' L^-1 A L^-T p = -1/0.002^2 * 0.002 < 0: negative curvature at iteration 1, so the
+    step runs along p to the boundary, s_hat = (-1, 0), and w = L^-T s_hat."""
+    a = np.diag([-1.0, 2.0])
+    res = orc.subspace_cg(a, np.array([1.0, 0.0]), delta=1.0)
+    assert res["exit"] == 2 and res["iters"] == 1
+    assert res["shift"] == pytest.approx(1.002, rel=1e-15)
+    assert np.allclose(res["shat"], [-1.0, 0.0], rtol=1e-15, atol=0.0)
+    assert np.allclose(res["w"], [-1.0 / math.sqrt(0.002), 0.0], rtol=1e-14, atol=0.0)
+
+
+def test_cg_second_direction_is_conjugate(orc):
+    """A = [[1, 2], [2, 1]] (eigenvalues 3 and -1, positive diagonal): alpha = 0 fails, then
+    alpha = 1e-3 doubles until (1 + alpha)^2 > 4, i.e. alpha = 1e-3 * 2^10 = 1.024. With
+    r = (1, 0.99) the first direction has positive curvature, the second negative, so CG
+    stops at iteration 2 on the boundary. Whatever the second direction's length, it must be
+    conjugate to the first under M = L^-1 A L^-T (the defining property of CG), and the first
+    step is the exact minimiser along the first direction."""
+    a = np.array([[1.0, 2.0], [2.0, 1.0]])
+    r = np.array([1.0, 0.99])
+    delta = 100.0
+    res = orc.subspace_cg(a, r, delta=delta)
+    assert res["shift"] == pytest.approx(1.024, rel=1e-15)
+    assert res["exit"] == 2 and res["iters"] == 2
+    L = np.linalg.cholesky(a + res["shift"] * np.eye(2))
+    Li = np.linalg.inv(L)
+    M = Li @ a @ Li.T
+    p0 = -Li @ r
+    assert p0 @ M @ p0 > 0
+    s1 = (p0 @ p0) / (p0 @ M @ p0) * p0
+    assert np.linalg.norm(s1) < delta
+    d = res["shat"] - s1
+    assert abs(p0 @ M @ d) <= 1e-10 * np.linalg.norm(M @ p0) * np.linalg.norm(d)
+    assert d @ M @ d < 0
+    assert np.linalg.norm(res["shat"]) == pytest.approx(delta, rel=1e-14)

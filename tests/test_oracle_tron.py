@@ -242,5 +242,5 @@ def test_flop_counter_is_algorithmic(orc):
               [r["x"][8 * k:8 * k + 8] for k in range(16)])
     r2 = orc.solve(bt2, nthreads=1)
     n = 8
-    first_eval = (2 * n * n + 7 * n + 4) + (2 * n * n + 5 * n + 1)
+    first_eval = (2 * n * n + 7 * n + 4) + (4 * n + 1)  # f, then the gradient sharing Qx
     assert np.all(r2["stats"][:, 0] == first_eval)
