@@ -80,6 +80,7 @@ def lib():
         L.or_eval_g.argtypes = [C.c_int32, C.c_int32, P, P, P]
         L.or_eval_h.argtypes = [C.c_int32, C.c_int32, P, P, P]
         L.or_br6_flows.argtypes = [P, P, P]
+        L.or_eval_batch.argtypes = [C.c_int32, C.c_int64, P, C.c_int32, P, P, P, P, P, P]
         L.or_ccf.restype = C.c_int32
         L.or_ccf.argtypes = [C.c_int32, P, C.c_double, P]
         L.or_trsv_lower.argtypes = [C.c_int32, P, P]
@@ -194,6 +195,20 @@ def eval_h(family, n, params, x):
     h = np.zeros(n * n)
     lib().or_eval_h(family, n, _p(_f64(params)), _p(_f64(x)), _p(h))
     return h.reshape(n, n)
+
+
+def eval_batch(batch, x):
+    """f and the infinity norm of the projected gradient of every instance of `batch` at
+    the packed points x (one array, instances back to back)."""
+    n = np.ascontiguousarray(batch.n, dtype=np.int32)
+    B = int(n.shape[0])
+    x = _f64(x)
+    assert x.shape[0] == int(n.astype(np.int64).sum())
+    f = np.zeros(B)
+    pg = np.zeros(B)
+    lib().or_eval_batch(batch.family, B, _p(n), 0, _p(_f64(batch.params)), _p(_f64(batch.lo)),
+                        _p(_f64(batch.hi)), _p(x), _p(f), _p(pg))
+    return f, pg
 
 
 def br6_flows(params, x):

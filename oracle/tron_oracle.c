@@ -1156,6 +1156,32 @@ double or_actual_reduction(int32_t n, double f, double ft, double pred, const do
     return actual_reduction(n, f, ft, pred, g, gt, s, &fl);
 }
 
+/* f and the infinity norm of the projected gradient at given points, instance by instance
+ * (packed like or_tron_batch), for the parity checks. */
+void or_eval_batch(int32_t family, int64_t batch, const int32_t *n_per, int32_t n_uniform,
+                   const double *params, const double *lo, const double *hi, const double *x,
+                   double *f_out, double *pg_out)
+{
+    int64_t po = 0, vo = 0;
+    double *g = NULL;
+    int gcap = 0;
+    for (int64_t b = 0; b < batch; b++) {
+        int n = n_per ? n_per[b] : n_uniform;
+        if (n > gcap) {
+            free(g);
+            gcap = n;
+            g = (double *)malloc(sizeof(double) * (size_t)gcap);
+        }
+        double fl = 0.0;
+        f_out[b] = fam_f(family, n, params + po, x + vo, &fl);
+        fam_g(family, n, params + po, x + vo, g, &fl);
+        pg_out[b] = or_projgrad_inf(n, x + vo, lo + vo, hi + vo, g);
+        po += or_param_size(family, n);
+        vo += n;
+    }
+    free(g);
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* Batch driver: instances are claimed from an atomic counter by host threads.          */
 /* ------------------------------------------------------------------------------------ */

@@ -59,6 +59,10 @@ int32_t or_tron_batch(int32_t family, int64_t batch, const int32_t *n_per, int32
 double or_eval_f(int32_t family, int32_t n, const double *params, const double *x);
 void or_eval_g(int32_t family, int32_t n, const double *params, const double *x, double *g);
 void or_eval_h(int32_t family, int32_t n, const double *params, const double *x, double *h);
+/* f and ||grad_[l,u] f||_inf at the points x of a packed batch (as or_tron_batch). */
+void or_eval_batch(int32_t family, int64_t batch, const int32_t *n_per, int32_t n_uniform,
+                   const double *params, const double *lo, const double *hi, const double *x,
+                   double *f_out, double *pg_out);
 /* Branch flows (p_ij, q_ij, p_ji, q_ji) at x for a BR6 parameter block. */
 void or_br6_flows(const double *params, const double *x, double *pq4);
 

@@ -31,6 +31,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#ifndef MT_LANE_CG_EXACT
+#define MT_LANE_CG_EXACT 0
+#endif
+#ifndef MT_LANE_QFORM
+#define MT_LANE_QFORM 0
+#endif
+#ifndef MT_LANE_FULLF
+#define MT_LANE_FULLF 0
+#endif
+
 namespace mt {
 
 #define MT_INLINE __device__ __forceinline__
@@ -94,6 +104,7 @@ template <int N>
 struct QP4 {
     static constexpr int T = N * (N + 1) / 2;
     static constexpr double pad = 0.0;
+    static constexpr int kLdsDoubles = 0;
     double q[T];
     double c[N];
     double hd[N];
@@ -136,6 +147,7 @@ template <int N>
 struct HS45M {
     static constexpr int T = N * (N + 1) / 2;
     static constexpr double pad = 1.0;
+    static constexpr int kLdsDoubles = 0;
     double h[T];
     MT_INLINE void load(const double *__restrict__, int) {}
     MT_INLINE double fg(const double (&x)[N], double (&g)[N])
@@ -161,35 +173,76 @@ struct HS45M {
     MT_INLINE double H(int i, int j) const { return h[tri(i, j)]; }
 };
 
+// The dynamic LDS of the lane kernels (used by families that keep their parameters there).
+MT_INLINE double *lane_lds()
+{
+    extern __shared__ double mt_lane_lds[];
+    return mt_lane_lds;
+}
+
 // BR6: the branch subproblem (eq. exp-branch) with the flows of eqs. pij..qji and two
 // flow copies z coupled to p_ij, p_ji. Derivatives are taken in (v_i, v_j, D = th_i - th_j)
 // and mapped to (th_i, th_j) with dD/dth_i = 1, dD/dth_j = -1.
-struct BR6 {
+// kLds: the 36 parameters live in the workgroup's LDS (pairs of doubles per lane, lane-major
+// within each pair block) and are read at each evaluation, instead of occupying 72 registers
+// for the whole solve; the solver's state then fits the register file without copies to
+// the accumulation registers. The LDS offset passes through an empty asm statement at each
+// evaluation so that the loads stay there instead of being hoisted out of the solve loop.
+template <bool kLds>
+struct BR6T {
     static constexpr int N = 6;
     static constexpr int T = 21;
     static constexpr double pad = 0.0;
-    double prm[36];
-    double cth, sth;  // cos, sin of th_i - th_j at the last fg point
+    static constexpr int kLdsDoubles = kLds ? 36 : 0;  // per lane
+    double prm_r[kLds ? 1 : 36];
+    int loff;              // kLds: LDS index of this lane's first parameter pair
+    double cth, sth;       // cos, sin of th_i - th_j at the last fg point
     double h[T];
 
     MT_INLINE void load(const double *__restrict__ p, int)
     {
-        MT_UNROLL for (int k = 0; k < 36; k++) prm[k] = p[k];
+        if constexpr (kLds) {
+            double *L = lane_lds();
+            loff = 2 * (int)threadIdx.x;
+            const int stride = 2 * (int)blockDim.x;
+            MT_UNROLL for (int k = 0; k < 18; k++) {
+                L[loff + k * stride] = p[2 * k];
+                L[loff + k * stride + 1] = p[2 * k + 1];
+            }
+        } else {
+            MT_UNROLL for (int k = 0; k < 36; k++) prm_r[k] = p[k];
+        }
+    }
+    MT_INLINE void params(double (&q)[36]) const
+    {
+        if constexpr (kLds) {
+            int o = loff;
+            asm volatile("" : "+v"(o));
+            const double *L = lane_lds();
+            const int stride = 2 * (int)blockDim.x;
+            MT_UNROLL for (int k = 0; k < 18; k++) {
+                q[2 * k] = L[o + k * stride];
+                q[2 * k + 1] = L[o + k * stride + 1];
+            }
+        } else {
+            MT_UNROLL for (int k = 0; k < 36; k++) q[k] = prm_r[k];
+        }
     }
     // flow k = a own^2 + V (al cos D + be sin D), own = v_i for k < 2 and v_j otherwise
-    MT_INLINE double fa(int k) const { return k == 0 ? prm[2] : k == 1 ? prm[3] : k == 2 ? prm[6] : prm[7]; }
-    MT_INLINE double fal(int k) const { return k == 0 ? -prm[0] : k == 1 ? -prm[1] : k == 2 ? -prm[4] : -prm[5]; }
-    MT_INLINE double fbe(int k) const { return k == 0 ? prm[1] : k == 1 ? -prm[0] : k == 2 ? -prm[5] : prm[4]; }
+    static MT_INLINE double fa(const double (&p)[36], int k) { return k == 0 ? p[2] : k == 1 ? p[3] : k == 2 ? p[6] : p[7]; }
+    static MT_INLINE double fal(const double (&p)[36], int k) { return k == 0 ? -p[0] : k == 1 ? -p[1] : k == 2 ? -p[4] : -p[5]; }
+    static MT_INLINE double fbe(const double (&p)[36], int k) { return k == 0 ? p[1] : k == 1 ? -p[0] : k == 2 ? -p[5] : p[4]; }
 
     // flows y[0..3], phi, psi = dphi/dD, and first-derivative coefficients of the flows
     // (c_k, with the z couplings folded into p_ij and p_ji) at x
-    MT_INLINE double flows(const double (&x)[6], double (&y)[4], double (&phi)[4], double (&psi)[4],
-                           double (&ck)[4], double (&cz)[2], double (&cw)[2], double (&cth_)[2]) const
+    MT_INLINE double flows(const double (&prm)[36], const double (&x)[6], double (&y)[4], double (&phi)[4],
+                           double (&psi)[4], double (&ck)[4], double (&cz)[2], double (&cw)[2],
+                           double (&cth_)[2]) const
     {
         const double vi = x[0], vj = x[1], V = vi * vj;
         double f = 0.0;
         MT_UNROLL for (int k = 0; k < 4; k++) {
-            const double al = fal(k), be = fbe(k), a = fa(k);
+            const double al = fal(prm, k), be = fbe(prm, k), a = fa(prm, k);
             const double own = k < 2 ? vi : vj;
             phi[k] = fma(al, cth, be * sth);
             psi[k] = fma(-al, sth, be * cth);
@@ -220,16 +273,18 @@ struct BR6 {
 
     MT_INLINE double fg(const double (&x)[6], double (&g)[6])
     {
+        double prm[36];
+        params(prm);
         sincos(x[2] - x[3], &sth, &cth);
         double y[4], phi[4], psi[4], ck[4], cz[2], cw[2], ct[2];
-        const double f = flows(x, y, phi, psi, ck, cz, cw, ct);
+        const double f = flows(prm, x, y, phi, psi, ck, cz, cw, ct);
         const double vi = x[0], vj = x[1], V = vi * vj;
         // effective coefficients of the flow gradients (z couplings subtract from p flows)
         const double e0 = ck[0] - cz[0], e1 = ck[1], e2 = ck[2] - cz[1], e3 = ck[3];
         const double sphi = e0 * phi[0] + e1 * phi[1] + e2 * phi[2] + e3 * phi[3];
         const double spsi = e0 * psi[0] + e1 * psi[1] + e2 * psi[2] + e3 * psi[3];
-        const double own_i = 2.0 * (e0 * fa(0) + e1 * fa(1)) * vi;
-        const double own_j = 2.0 * (e2 * fa(2) + e3 * fa(3)) * vj;
+        const double own_i = 2.0 * (e0 * fa(prm, 0) + e1 * fa(prm, 1)) * vi;
+        const double own_j = 2.0 * (e2 * fa(prm, 2) + e3 * fa(prm, 3)) * vj;
         g[0] = fma(vj, sphi, own_i) + 2.0 * cw[0] * vi;
         g[1] = fma(vi, sphi, own_j) + 2.0 * cw[1] * vj;
         const double gD = V * spsi;
@@ -242,8 +297,10 @@ struct BR6 {
 
     MT_INLINE void hess(const double (&x)[6])
     {
+        double prm[36];
+        params(prm);
         double y[4], phi[4], psi[4], ck[4], cz[2], cw[2], ct[2];
-        flows(x, y, phi, psi, ck, cz, cw, ct);
+        flows(prm, x, y, phi, psi, ck, cz, cw, ct);
         const double vi = x[0], vj = x[1], V = vi * vj;
         const double e[4] = {ck[0] - cz[0], ck[1], ck[2] - cz[1], ck[3]};
         // Gauss-Newton weights: the z couplings add their penalty to p_ij and p_ji
@@ -253,7 +310,7 @@ struct BR6 {
         double hDD = 0.0;
         double dp[2][3];            // gradients of p_ij, p_ji in (vi, vj, D)
         MT_UNROLL for (int k = 0; k < 4; k++) {
-            const double a2 = 2.0 * fa(k);
+            const double a2 = 2.0 * fa(prm, k);
             const double di = k < 2 ? fma(vj, phi[k], a2 * vi) : vj * phi[k];
             const double dj = k < 2 ? vi * phi[k] : fma(vi, phi[k], a2 * vj);
             const double dD = V * psi[k];
@@ -296,6 +353,11 @@ struct BR6 {
     MT_INLINE double H(int i, int j) const { return h[tri(i, j)]; }
 };
 
+#ifndef MT_BR6_PARAMS_LDS
+#define MT_BR6_PARAMS_LDS 0
+#endif
+using BR6 = BR6T<MT_BR6_PARAMS_LDS != 0>;
+
 // BR8L: BR6 plus the line limits of both ends as equalities with slacks,
 //   h_lm = p_lm^2 + q_lm^2 + sigma_lm - smax^2,  lm in {ij, ji},
 // entering through the augmented-Lagrangian terms lambda_lm h_lm + rho_h/2 h_lm^2 (section 1
@@ -307,7 +369,8 @@ struct BR8L {
     static constexpr int N = 8;
     static constexpr int T = 36;
     static constexpr double pad = 0.0;
-    BR6 b6;                // the BR6 part; its Hessian block also receives the limit terms
+    static constexpr int kLdsDoubles = 0;
+    BR6T<false> b6;        // the BR6 part; its Hessian block also receives the limit terms
     double smax2, lam[2], rhoh;
     double hs[2][4];       // slack rows of the Hessian against (v_i, v_j, th_i, th_j)
 
@@ -325,7 +388,7 @@ struct BR8L {
     // (vi vi, vj vj, vi vj, vi D, vj D, D D)
     MT_INLINE void flow(int k, double vi, double vj, double &y, double (&d)[3], double (&d2)[6]) const
     {
-        const double al = b6.fal(k), be = b6.fbe(k), a = b6.fa(k), V = vi * vj;
+        const double al = b6.fal(b6.prm_r, k), be = b6.fbe(b6.prm_r, k), a = b6.fa(b6.prm_r, k), V = vi * vj;
         const double phi = fma(al, b6.cth, be * b6.sth);
         const double psi = fma(-al, b6.sth, be * b6.cth);
         const double a2 = 2.0 * a;
@@ -513,10 +576,14 @@ struct LaneTron {
             st[i] = xt[i] - x[i];
         }
         if (!(dot(st, st) <= delta * delta)) return false;  // ||s|| <= delta
+        const double gts = dot(g, st);
+#if MT_LANE_QFORM
+        const double q = fma(0.5, qform(st), gts);
+#else
         double hs[N];
         hmul(st, hs);
-        const double gts = dot(g, st);
         const double q = fma(0.5, dot(st, hs), gts);
+#endif
         return q <= kMu0 * gts;
     }
 
@@ -559,9 +626,24 @@ struct LaneTron {
         alphac = a;
     }
 
+    // v'Hv from the packed lower triangle: sum_i v_i (H_ii v_i + 2 sum_{j<i} H_ij v_j)
+    MT_INLINE double qform(const double (&v)[N]) const
+    {
+        double acc = 0.0;
+        MT_UNROLL for (int i = 0; i < N; i++) {
+            double u = 0.0;
+            MT_UNROLL for (int j = 0; j < i; j++) u = fma(fam.H(i, j), v[j], u);
+            acc = fma(v[i], fma(fam.H(i, i), v[i], 2.0 * u), acc);
+        }
+        return acc;
+    }
+
     // Cholesky of the masked, shifted matrix: rows/columns outside fm are the identity.
+    // kFull: every variable is free (fm has all N bits), so no entry is masked.
+    template <bool kFull = false>
     MT_INLINE bool chol(uint32_t fm, double alpha)
     {
+        if constexpr (kFull) fm = (1u << N) - 1u;
         bool ok = true;
         MT_UNROLL for (int j = 0; j < N; j++) {
             const bool fj = (fm >> j) & 1u;
@@ -580,8 +662,11 @@ struct LaneTron {
         return ok;
     }
 
-    MT_INLINE void precond(uint32_t fm)
+    // Returns the shift that succeeded, or -1 when the diagonal fallback was used.
+    template <bool kFull = false>
+    MT_INLINE double precond(uint32_t fm)
     {
+        if constexpr (kFull) fm = (1u << N) - 1u;
         double dmn = 0.0, dmx = 0.0;
         bool first = true;
         MT_UNROLL for (int i = 0; i < N; i++) {
@@ -596,7 +681,7 @@ struct LaneTron {
         double alpha = dmn > 0.0 ? 0.0 : beta - dmn;
         for (int t = 0; t < kShiftTries; t++) {
             chol_tries++;
-            if (chol(fm, alpha)) return;
+            if (chol<kFull>(fm, alpha)) return alpha;
             alpha = 2.0 * alpha > beta ? 2.0 * alpha : beta;
         }
         MT_UNROLL for (int i = 0; i < N; i++) {
@@ -606,11 +691,17 @@ struct LaneTron {
             L[tri(i, i)] = piv;
             dinv[i] = 1.0 / piv;
         }
+        return -1.0;
     }
 
     // Steihaug CG in the preconditioned variable; result in sh (zero outside fm).
-    MT_INLINE int pcg(uint32_t fm, int m, const double (&r)[N], double (&sh)[N], double cg_rtol)
+    // exact: L L^T is the unshifted block itself, so the preconditioned matrix is the
+    // identity and the first CG step (length 1 along r_hat, or to the boundary) is the
+    // whole solve.
+    template <bool kFull = false>
+    MT_INLINE int pcg(uint32_t fm, int m, const double (&r)[N], double (&sh)[N], double cg_rtol, bool exact)
     {
+        if constexpr (kFull) fm = (1u << N) - 1u;
         double rh[N], p[N];
         MT_UNROLL for (int i = 0; i < N; i++) {
             rh[i] = ((fm >> i) & 1u) ? -r[i] : 0.0;
@@ -621,6 +712,20 @@ struct LaneTron {
         double rr = dot(rh, rh);
         const double tol2 = cg_rtol * cg_rtol * rr;  // (cg_rtol ||r0||)^2
         if (rr == 0.0) return kCgConv;
+#if MT_LANE_CG_EXACT
+        if (exact) {
+            cg_iters++;
+            if (rr >= delta * delta) {
+                const double sig = trqsol(sh, p);
+                MT_UNROLL for (int i = 0; i < N; i++) sh[i] = sig * p[i];
+                return kCgBnd;
+            }
+            MT_UNROLL for (int i = 0; i < N; i++) sh[i] = p[i];
+            return kCgConv;
+        }
+#else
+        (void)exact;
+#endif
         for (int j = 0; j < m; j++) {
             cg_iters++;
             double z[N], q[N];
@@ -676,10 +781,19 @@ struct LaneTron {
             MT_UNROLL for (int i = 0; i < N; i++) s[i] = xs[i] - x[i];
             hmul(s, r);
             MT_UNROLL for (int i = 0; i < N; i++) r[i] += g[i];
-            precond(fm);
             lfm = fm;
             double w[N];
-            const int ex = pcg(fm, m, r, w, cg_rtol);
+            int ex;
+#if MT_LANE_FULLF
+            if (fm == (1u << N) - 1u) {
+                const double sh = precond<true>(fm);
+                ex = pcg<true>(fm, m, r, w, cg_rtol, sh == 0.0);
+            } else
+#endif
+            {
+                const double sh = precond(fm);
+                ex = pcg(fm, m, r, w, cg_rtol, sh == 0.0);
+            }
             bwd(w);  // w = L^-T s_hat (zero outside F)
             // projected search on the model
             double beta = 1.0;
@@ -692,9 +806,14 @@ struct LaneTron {
                     xt[i] = clampf(fma(beta, w[i], xs[i]), lo[i], hi[i]);
                     d[i] = xt[i] - xs[i];
                 }
+#if MT_LANE_QFORM
+                const double rd = dot(r, d);
+                const double dq = fma(0.5, qform(d), rd);
+#else
                 hmul(d, hd);
                 const double rd = dot(r, d);
                 const double dq = fma(0.5, dot(d, hd), rd);
+#endif
                 if (dq <= kMu0 * rd) { acc = true; break; }
                 beta *= 0.5;
             }
@@ -769,9 +888,13 @@ struct LaneTron {
             double s[N], hs[N];
             MT_UNROLL for (int i = 0; i < N; i++) s[i] = xs[i] - x[i];
             const double snorm = step_norm(s);
-            hmul(s, hs);
             const double gts = dot(g, s);
+#if MT_LANE_QFORM
+            const double pred = -fma(0.5, qform(s), gts);
+#else
+            hmul(s, hs);
             const double pred = -fma(0.5, dot(s, hs), gts);
+#endif
             iters++;
             if (!(pred > 0.0)) { status = kStalled; break; }
             double gt[N];

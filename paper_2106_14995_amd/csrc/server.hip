@@ -107,6 +107,7 @@ struct Request {
     uint64_t session = 0;
     size_t lds = 0;
     int state = 0;  // 0 queued, 1 on the device, 2 done
+    tron_err err = TRON_OK;  // done without a solve: why (the result call reports it)
     // session placement, copied at admission (the scheduler never reads the session map
     // outside the lock)
     size_t sess_off = 0;
@@ -180,6 +181,7 @@ struct tron_server {
     std::vector<Group *> inflight;
     std::unordered_map<int64_t, std::unique_ptr<Request>> tickets;
     std::unordered_map<uint64_t, Session> sessions;
+    size_t session_bytes = 0;  // device arena bytes held by resident sessions
     size_t lds_inflight = 0;
     int64_t next_ticket = 1;
     int64_t done_requests = 0, done_instances = 0;
@@ -456,6 +458,22 @@ void scheduler(tron_server *s)
             s->inflight.push_back(g);
             progress = true;
         }
+        // Nothing on the device and the head request still cannot be placed: only resident
+        // sessions hold arena memory now (or leave it fragmented), and waiting frees none,
+        // so the request fails instead of blocking its waiter forever.
+        if (!progress && s->inflight.empty() && !s->queue.empty()) {
+            Request *r = s->queue.front();
+            s->queue.pop_front();
+            r->err = TRON_ERR_BUSY;
+            r->state = 2;
+            r->t_done = clock_t_::now();
+            if (r->session) {
+                auto it = s->sessions.find(r->session);
+                if (it != s->sessions.end()) it->second.outstanding--;
+            }
+            s->done_cv.notify_all();
+            progress = true;
+        }
         if (!progress) {
             if (s->inflight.empty()) s->cv.wait_for(lk, std::chrono::milliseconds(1));
             else {
@@ -570,8 +588,16 @@ extern "C" tron_err tron_server_submit(tron_server *s, int64_t batch, const int3
     r->has_x0 = x0 != nullptr;
     if (x0) r->x0.assign(x0, x0 + nsum);
     r->session = session;
-    if (request_device_bytes(*r) > s->cfg.hbm_budget) return mt_fail(TRON_ERR_BUSY, "request larger than the device budget");
+    const size_t need = request_device_bytes(*r);
+    if (need > s->cfg.hbm_budget) return mt_fail(TRON_ERR_BUSY, "request larger than the device budget");
     std::lock_guard<std::mutex> lk(s->mu);
+    // resident sessions keep their arena memory until closed: the request must fit next to
+    // them (and next to its own session, when it opens one)
+    size_t new_session = 0;
+    if (session && s->sessions.find(session) == s->sessions.end())
+        new_session = align_up(sizeof(double) * nsum) + sizeof(double) * 2 * batch;
+    if (need + new_session > s->cfg.hbm_budget - std::min(s->session_bytes, s->cfg.hbm_budget))
+        return mt_fail(TRON_ERR_BUSY, "request does not fit in the device budget next to the resident sessions");
     if (session) {
         auto it = s->sessions.find(session);
         if (it == s->sessions.end()) {
@@ -579,9 +605,10 @@ extern "C" tron_err tron_server_submit(tron_server *s, int64_t batch, const int3
             Session ss;
             ss.n = r->n;
             ss.nsum = nsum;
-            ss.bytes = align_up(sizeof(double) * nsum) + sizeof(double) * 2 * batch;
+            ss.bytes = new_session;
             if (!s->dev.alloc(ss.bytes, &ss.off)) return mt_fail(TRON_ERR_BUSY, "no device memory for the session");
             s->sessions[session] = ss;
+            s->session_bytes += ss.bytes;
         } else if (it->second.n != r->n) {
             return mt_fail(TRON_ERR_INVALID, "session sizes differ");
         } else if (it->second.outstanding > 0) {
@@ -642,6 +669,11 @@ extern "C" tron_err tron_server_result(tron_server *s, int64_t ticket, double *x
     if (it == s->tickets.end()) return mt_fail(TRON_ERR_INVALID, "unknown ticket");
     Request *r = it->second.get();
     if (r->state != 2) return mt_fail(TRON_ERR_BUSY, "request not finished");
+    if (r->err != TRON_OK) {
+        const tron_err e = r->err;
+        s->tickets.erase(it);
+        return mt_fail(e, "request could not be admitted: resident sessions leave too little device memory");
+    }
     if (x) std::copy(r->x.begin(), r->x.end(), x);
     if (f) std::copy(r->f.begin(), r->f.end(), f);
     if (status) std::copy(r->status.begin(), r->status.end(), status);
@@ -659,6 +691,7 @@ extern "C" tron_err tron_server_close_session(tron_server *s, uint64_t session)
     if (it == s->sessions.end()) return mt_fail(TRON_ERR_INVALID, "unknown session");
     if (it->second.outstanding > 0) return mt_fail(TRON_ERR_BUSY, "session has a request outstanding");
     s->dev.release(it->second.off, it->second.bytes);
+    s->session_bytes -= it->second.bytes;
     s->sessions.erase(it);
     return TRON_OK;
 }

@@ -6,8 +6,10 @@ There is no CPU fallback: if the library is not built, loading it raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -72,6 +74,26 @@ EXPORTS = ("tron_default_options", "tron_last_error", "tron_param_size", "tron_b
            "tron_default_al_options", "tron_al_solve", "tron_design_chol", "tron_design_trsv")
 CHOL_LEFT_LDS, CHOL_RIGHT_LDS, CHOL_LEFT_GLOBAL, CHOL_BLOCKED_MFMA = 0, 1, 2, 3
 TRSV_IMPLICIT, TRSV_PADDED, TRSV_EXPLICIT, TRSV_GLOBAL = 0, 1, 2, 3
+
+
+# Handles still open when the interpreter exits are closed by an exit hook, which runs
+# before the HIP runtime's own teardown; destructors that run later (during module
+# teardown) then do nothing instead of calling into a runtime that may be gone.
+_live = weakref.WeakSet()
+_at_exit = False
+
+
+def _close_all():
+    global _at_exit
+    for h in list(_live):
+        try:
+            h.close()
+        except Exception:
+            pass
+    _at_exit = True
+
+
+atexit.register(_close_all)
 
 
 def lib_path() -> str:
@@ -189,6 +211,7 @@ class Batch:
         _check(L.tron_batch_create_ex(C.byref(self._h), self.family, self.batch, nptr, nuni,
                                       C.byref(o), C.byref(spec) if spec is not None else None,
                                       _stream_ptr(stream)))
+        _live.add(self)
 
     def solve(self, params, lo, hi, x0, x=None, f=None, status=None, iters=None, stream=None):
         import torch
@@ -263,6 +286,8 @@ class Batch:
             self._h = C.c_void_p()
 
     def __del__(self):
+        if _at_exit:
+            return
         try:
             self.close()
         except Exception:
@@ -317,6 +342,7 @@ class Admm:
         self._h = C.c_void_p()
         o = branch_opts if branch_opts is not None else options()
         _check(L.admm_create(C.byref(self._h), C.byref(self._net), C.byref(o), _stream_ptr(stream)))
+        _live.add(self)
         del keep
 
     def step(self, iters: int, resid=None, stream=None):
@@ -346,6 +372,8 @@ class Admm:
             self._h = C.c_void_p()
 
     def __del__(self):
+        if _at_exit:
+            return
         try:
             self.close()
         except Exception:
@@ -371,6 +399,7 @@ class Server:
         self._h = C.c_void_p()
         self._sizes = {}
         _check(L.tron_server_create(C.byref(self._h), self.family, C.byref(cfg)))
+        _live.add(self)
 
     def submit(self, n, params, lo, hi, x0=None, session=0) -> int:
         n = np.ascontiguousarray(n, dtype=np.int32)
@@ -418,6 +447,8 @@ class Server:
             self._h = C.c_void_p()
 
     def __del__(self):
+        if _at_exit:
+            return
         try:
             self.close()
         except Exception:

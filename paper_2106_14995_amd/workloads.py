@@ -329,11 +329,15 @@ class Network:
 
 
 def network(nbus: int = 2000, nbranch: int = 3000, ngen: int = 500, config_id: int = 2,
-            rho: float = 400.0) -> Network:
+            rho: float = 400.0, hub_ends: int = 0, hub_gens: int = 0,
+            hub_shunt=(0.0, 0.0)) -> Network:
     """Random recursive spanning tree (bus k joins a uniform j < k) plus distinct extra
     non-adjacent edges; branch g, b as in BR6; generators on distinct uniform buses with
     c2 ~ U[0.01,0.1], c1 ~ U[5,40], pmax ~ U[1,5], pmin = 0, q in [-pmax/2, pmax/2];
-    loads pd = 0.6 sum(pmax)/nbus U[0.5,1.5], qd = 0.3 pd; no shunts."""
+    loads pd = 0.6 sum(pmax)/nbus U[0.5,1.5], qd = 0.3 pd; no shunts.
+    hub_ends / hub_gens > 0 add a hub at bus 0 (drawn from a stream of its own, so the
+    rest of the network is unchanged): hub_ends more branches from bus 0 to distinct buses
+    it does not yet touch, hub_gens more generators on bus 0, and the shunt (g, b) there."""
     rng = rng_for(config_id, 0)
     edges = set()
     frm, to = [], []
@@ -358,5 +362,25 @@ def network(nbus: int = 2000, nbranch: int = 3000, ngen: int = 500, config_id: i
     lim = np.stack([np.zeros(ngen), pmax, -pmax / 2.0, pmax / 2.0], axis=1)
     pd = 0.6 * pmax.sum() / nbus * rng.uniform(0.5, 1.5, nbus)
     load = np.stack([pd, 0.3 * pd, np.zeros(nbus), np.zeros(nbus)], axis=1)
-    return Network(nbus, frm, to, adm, lo, hi, gen_bus, np.stack([c2, c1], axis=1), lim, load,
-                   rho=rho)
+    cost = np.stack([c2, c1], axis=1)
+    if hub_ends or hub_gens:
+        hr = rng_for(config_id, 1)
+        touched = {b for e in edges for b in e if 0 in e}
+        cand = np.array([k for k in range(1, nbus) if k not in touched])
+        ends = hr.choice(cand, size=hub_ends, replace=False)
+        for k in sorted(int(v) for v in ends):
+            frm.append(0); to.append(k)
+        ne = len(ends)
+        g2 = hr.uniform(0.5, 5.0, ne)
+        b2 = hr.uniform(-20.0, -1.0, ne)
+        adm = np.concatenate([adm, np.stack([g2, b2, g2, b2, g2, b2, g2, b2], axis=1)])
+        lo = np.tile(BR6_LO, (len(frm), 1))
+        hi = np.tile(BR6_HI, (len(frm), 1))
+        pm2 = hr.uniform(1.0, 5.0, hub_gens)
+        gen_bus = np.concatenate([gen_bus, np.zeros(hub_gens, dtype=np.int32)])
+        cost = np.concatenate([cost, np.stack([hr.uniform(0.01, 0.1, hub_gens),
+                                               hr.uniform(5.0, 40.0, hub_gens)], axis=1)])
+        lim = np.concatenate([lim, np.stack([np.zeros(hub_gens), pm2, -pm2 / 2.0, pm2 / 2.0], axis=1)])
+        load = load.copy()
+        load[0, 2], load[0, 3] = hub_shunt
+    return Network(nbus, frm, to, adm, lo, hi, gen_bus, cost, lim, load, rho=rho)

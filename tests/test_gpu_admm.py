@@ -44,8 +44,7 @@ def test_init_matches_oracle(T, net):
     a.close()
 
 
-@pytest.mark.parametrize("warm_iters", [0, 7])
-def test_one_iteration_parity(T, net, warm_iters):
+def one_iteration_parity(T, net, warm_iters):
     import torch
     st0 = oracle.admm_init(net)
     if warm_iters:
@@ -64,6 +63,27 @@ def test_one_iteration_parity(T, net, warm_iters):
     r = to_np(res)[0]
     assert np.allclose(r, ores[0], rtol=1e-6, atol=1e-9)
     a.close()
+
+
+@pytest.mark.parametrize("warm_iters", [0, 7])
+def test_one_iteration_parity(T, net, warm_iters):
+    one_iteration_parity(T, net, warm_iters)
+
+
+def test_one_iteration_parity_full_network(T):
+    """The benchmark's network: 2,000 buses, 3,000 branches, 500 generators (bus degree up
+    to about a dozen branch ends)."""
+    one_iteration_parity(T, W.network(), 4)
+
+
+def test_one_iteration_parity_hub_bus(T):
+    """A hub bus with more than 16 branch ends, more than 4 generators and a shunt: the bus
+    update's general path, which loads its neighbours one by one."""
+    hub = W.network(nbus=300, nbranch=420, ngen=60, config_id=95, hub_ends=30, hub_gens=7,
+                    hub_shunt=(0.04, 0.15))
+    deg = np.bincount(np.concatenate([hub.br_from, hub.br_to]), minlength=hub.nbus)
+    assert deg[0] > 16 and np.sum(hub.gen_bus == 0) > 4
+    one_iteration_parity(T, hub, 3)
 
 
 def test_branch_solutions_are_kkt_points(T, net):
@@ -87,18 +107,20 @@ def test_branch_solutions_are_kkt_points(T, net):
 
 
 def test_checkpoint_resume_bitwise(T, net):
+    """1,000 iterations in one run against 500, a checkpoint to host memory, a new handle
+    and 500 more: the state and every residual agree bitwise."""
     import torch
     a = T.Admm(net)
-    r_all = to_np(a.step(6))
+    r_all = to_np(a.step(1000))
     full = to_np(a.get_state())
     a.close()
     b = T.Admm(net)
-    r1 = to_np(b.step(3))
-    mid = b.get_state().clone()
+    r1 = to_np(b.step(500))
+    mid = b.get_state().cpu().clone()
     b.close()
     c = T.Admm(net)
-    c.set_state(mid)
-    r2 = to_np(c.step(3))
+    c.set_state(mid.cuda())
+    r2 = to_np(c.step(500))
     resumed = to_np(c.get_state())
     c.close()
     assert np.array_equal(full, resumed)

@@ -10,8 +10,8 @@ import time
 import numpy as np
 import pytest
 
-import oracle
 from paper_2106_14995_amd import workloads as W
+from parity import check_parity, oracle_ref
 
 pytestmark = pytest.mark.gpu
 
@@ -68,20 +68,16 @@ def test_alone_equals_mix_and_batch_api(T):
 
 
 def test_server_matches_oracle(T):
+    """Every instance of a mixed-size request meets the strictly convex bars against the
+    oracle (f to 1e-8 relative, x to 1e-6, projected gradient 1e-6)."""
     bt = mixed(200, 82, nmax=128)
     srv = T.Server(W.QP4)
     t = srv.submit_batch(bt)
     srv.wait(t)
     r = srv.result(t)
     srv.close()
-    ref = oracle.solve(bt)
-    vo = bt.voff()
     assert np.all(r["status"] == 0)
-    for b in range(bt.batch):
-        n, p, lo, hi, _ = bt.instance(b)
-        xg = r["x"][vo[b]:vo[b + 1]]
-        assert oracle.projgrad_inf(xg, lo, hi, oracle.eval_g(0, n, p, xg)) <= 1e-6
-        assert abs(oracle.eval_f(0, n, p, xg) - ref["f"][b]) <= 1e-8 * max(1, abs(ref["f"][b]))
+    check_parity(bt, r, oracle_ref(bt), convex=True, label="server request")
     assert r["latency"] > 0
 
 
@@ -137,3 +133,36 @@ def test_destroy_with_work_pending(T):
     for i in range(6):
         srv.submit_batch(mixed(500, 100 + i))
     srv.close()  # waits for what is on the device, drops the queue, returns
+
+
+def test_resident_sessions_limit_admission(T):
+    """Sessions keep their device memory until closed. Sessions are opened until the next one
+    no longer fits; then a request that fits the budget alone but not next to the resident
+    sessions is refused at submission with BUSY (instead of waiting for memory that never
+    frees), and admitted once the sessions close."""
+    budget = 1 << 20
+    srv = T.Server(W.QP4, hbm_budget=budget, max_inflight=2, streams=1)
+    opened = []
+    for k in range(1, 200):
+        bt = W.qp4_batch(800, 4, config_id=120 + k)
+        try:
+            t = srv.submit_batch(bt, session=k)
+        except T.TronError as e:
+            assert e.code == 5
+            break
+        srv.wait(t)
+        assert np.all(srv.result(t)["status"] == 0)
+        opened.append(k)
+    assert len(opened) >= 2
+    held = srv.stats()["device_bytes"]
+    big = W.qp4_batch(1600, 4, config_id=119)   # about half the budget on its own
+    with pytest.raises(T.TronError) as e:
+        srv.submit_batch(big)
+    assert e.value.code == 5
+    for k in opened:
+        srv.close_session(k)
+    assert srv.stats()["device_bytes"] < held
+    t2 = srv.submit_batch(big)
+    srv.wait(t2)
+    assert np.all(srv.result(t2)["status"] == 0)
+    srv.close()

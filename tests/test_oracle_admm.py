@@ -141,3 +141,27 @@ def test_branch_phase_solves_each_branch(orc, small):
         assert orc.projgrad_inf(x, net.br_lo[l], net.br_hi[l], g) <= 1e-6
         fl = orc.br6_flows(p, x)
         assert np.allclose(b["y"][l], [*fl, x[0] ** 2, x[1] ** 2, x[2], x[3]], rtol=0, atol=0)
+
+
+def test_bus_update_on_a_hub_bus(orc):
+    """A hub bus with 24 more branch ends, 6 more generators and a shunt: the oracle's bus
+    update still equals the generic KKT solve, and the balance rows hold after it."""
+    net = W.network(nbus=80, nbranch=110, ngen=12, config_id=94, hub_ends=24, hub_gens=6,
+                    hub_shunt=(0.04, 0.15))
+    st = orc.admm_init(net)
+    st, _ = orc.admm_run(net, st, 3)
+    before = orc.admm_views(net, st)
+    after = orc.admm_views(net, orc.admm_phase(net, st, 2)[0])
+    b = 0
+    names, sol, gens, ends = bus_kkt(net, before, b)
+    assert len(ends) > 16 and len(gens) > 4
+    for k, nm in enumerate(names):
+        got = {"pg": lambda: after["pgt"][nm[1]], "qg": lambda: after["qgt"][nm[1]],
+               "pe": lambda: after["yt"][nm[1], 2 * nm[2]],
+               "qe": lambda: after["yt"][nm[1], 2 * nm[2] + 1]}[nm[0]]()
+        assert got == pytest.approx(sol[k], rel=1e-10, abs=1e-10)
+    assert after["wt"][b] == pytest.approx(sol[-2], rel=1e-10, abs=1e-12)
+    pd, qd, gs, bs = net.bus_load[b]
+    P = sum(after["pgt"][g] for g in gens) - sum(after["yt"][l, 2 * e] for l, e in ends) - gs * after["wt"][b]
+    Qr = sum(after["qgt"][g] for g in gens) - sum(after["yt"][l, 2 * e + 1] for l, e in ends) + bs * after["wt"][b]
+    assert P == pytest.approx(pd, abs=1e-12) and Qr == pytest.approx(qd, abs=1e-12)

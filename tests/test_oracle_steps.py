@@ -323,3 +323,20 @@ def test_cg_second_direction_is_conjugate(orc):
     assert abs(p0 @ M @ d) <= 1e-10 * np.linalg.norm(M @ p0) * np.linalg.norm(d)
     assert d @ M @ d < 0
     assert np.linalg.norm(res["shat"]) == pytest.approx(delta, rel=1e-14)
+
+
+def test_eval_batch_matches_single_evaluations(orc):
+    """The batch evaluator used by the parity checks gives, per instance, the same f and
+    projected-gradient norm as the single-instance evaluators."""
+    from paper_2106_14995_amd import workloads as W
+    sizes = W.loguniform_sizes(40, 1, 20, config_id=12)
+    for bt in (W.qp4_batch(40, sizes, config_id=12), W.br6_batch(30, config_id=1)):
+        rng = np.random.default_rng(5)
+        x = np.clip(bt.x0 + 0.1 * rng.standard_normal(bt.x0.shape), bt.lo, bt.hi)
+        f, pg = orc.eval_batch(bt, x)
+        vo = bt.voff()
+        for b in range(bt.batch):
+            n, p, lo, hi, _ = bt.instance(b)
+            xb = x[vo[b]:vo[b + 1]]
+            assert f[b] == orc.eval_f(bt.family, n, p, xb)
+            assert pg[b] == orc.projgrad_inf(xb, lo, hi, orc.eval_g(bt.family, n, p, xb))
