@@ -244,3 +244,35 @@ def test_flop_counter_is_algorithmic(orc):
     n = 8
     first_eval = (2 * n * n + 7 * n + 4) + (4 * n + 1)  # f, then the gradient sharing Qx
     assert np.all(r2["stats"][:, 0] == first_eval)
+
+
+def test_projected_gradient_ball_around_the_minimiser():
+    """The bound the convex parity bar uses for trajectory splits: for strongly convex f with
+    modulus mu on a box, ||x - x*||_2 <= ||grad_[l,u] f(x)||_2 / mu at any point x of the box,
+    with mu >= lambda_min(Q) for QP4. Checked on the oracle's iterates at loose tolerances
+    against its solution at gtol = 1e-13, and shown not to be vacuous (the ratio of the
+    distance to the bound reaches a sizeable fraction)."""
+    import oracle
+    from paper_2106_14995_amd import workloads as W
+    from parity import projgrad_vec, qp4_modulus
+    sizes = W.loguniform_sizes(300, 2, 40, config_id=12)
+    bt = W.qp4_batch(300, sizes, config_id=12)
+    star = oracle.solve(bt, gtol=1e-13)
+    vo, po = bt.voff(), bt.poff()
+    ratios = []
+    for gtol in (1e-2, 1e-4, 1e-6):
+        r = oracle.solve(bt, gtol=gtol)
+        for b in range(bt.batch):
+            n = int(bt.n[b])
+            p = bt.params[po[b]:po[b + 1]]
+            lo, hi = bt.lo[vo[b]:vo[b + 1]], bt.hi[vo[b]:vo[b + 1]]
+            x, xs = r["x"][vo[b]:vo[b + 1]], star["x"][vo[b]:vo[b + 1]]
+            mu = qp4_modulus(p, n)
+            assert mu >= 0.1 - 1e-12
+            pg = np.linalg.norm(projgrad_vec(x, lo, hi, oracle.eval_g(W.QP4, n, p, x)))
+            pgs = np.linalg.norm(projgrad_vec(xs, lo, hi, oracle.eval_g(W.QP4, n, p, xs)))
+            d = np.linalg.norm(x - xs)
+            assert d <= pg / mu + pgs / mu + 1e-13, (gtol, b, d, pg / mu)
+            if pg > 0:
+                ratios.append(d / (pg / mu))
+    assert max(ratios) > 0.05
