@@ -116,16 +116,29 @@ tron_err tron_batch_create(tron_batch **out, tron_family family, int64_t batch,
 /* Launch plan of a handle: instances with n <= lane_max_n are solved one per GPU lane (a
  * kernel per exact n); larger ones one per wavefront, grouped into buckets by the first of
  * `edges` (increasing, <= 128) that holds them, with LDS sized for that edge. Buckets run
- * concurrently on `streams` streams; lane kernels use workgroups of lane_block (64 or 256). */
+ * concurrently on `streams` streams; lane kernels use workgroups of lane_block (64 or 256).
+ * pool_waves > 0 selects the persistent size-bucketed form instead (section 4.1, a single
+ * kernel rather than one per size) for batches of mixed sizes up to n = 128: one launch
+ * solves every wavefront instance, with one workgroup of pool_waves (8 or 12) wavefronts
+ * per CU sharing the CU's LDS as a pool; each wave claims instances from the batch's list
+ * ordered largest n first and reserves exactly the LDS its instance needs; a second launch
+ * solves every lane instance, in packs of 64 of one size. Edges and streams are then unused. */
 typedef struct {
     int32_t lane_max_n;   /* 0..8 */
     int32_t nedges;       /* 1..16 */
     int32_t edges[16];
     int32_t streams;      /* 1..8 */
     int32_t lane_block;   /* 64 or 256 */
+    int32_t pool_waves;   /* 0 (bucketed), 8 or 12 (persistent)                                */
+    int32_t lane_group;   /* lanes per instance for n <= lane_max_n: 1 (lane kernel), 2, 4 or 8
+                             (the group kernel: one instance per group of lanes, rows split
+                             over the group, section 4.2's thread configuration)             */
+    int32_t group16;      /* 0, 8 or 16: instances with lane_max_n < n <= 16 go to the group
+                             kernel of that width instead of the wavefront kernel            */
 } tron_plan_spec;
 
-/* lane_max_n 8, edges 16/24/32/40/48/56/64/80/96/112/128, 4 streams, lane_block 64. */
+/* lane_max_n 8, edges 16/24/32/40/48/56/64/80/96/112/128, 4 streams, lane_block 64,
+ * pool_waves 0, lane_group 1, group16 0. */
 void tron_default_plan_spec(tron_plan_spec *spec);
 /* tron_batch_create with an explicit plan (spec NULL = default). INVALID for a bad spec,
  * UNSUPPORTED when some n exceeds the largest edge. */

@@ -30,7 +30,7 @@ struct LaneArgs {
 constexpr int kLdsMaxN = 128;
 constexpr int kMaxN = 512;
 // doubles of one instance's matrix array for bucket size nmax (n rows, odd stride > n)
-inline int64_t mt_wave_matrix_doubles(int nmax) { return (int64_t)nmax * (int64_t)((nmax + 1) | 1); }
+__host__ __device__ inline int64_t mt_wave_matrix_doubles(int nmax) { return (int64_t)nmax * (int64_t)((nmax + 1) | 1); }
 
 typedef void (*lane_launch_fn)(const LaneArgs &, hipStream_t);
 
@@ -56,3 +56,7 @@ tron_err mt_fail(tron_err code, const char *fmt, ...);
         if (e_ != hipSuccess)                                                                 \
             return mt_fail(TRON_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
     } while (0)
+
+// The group-solver kernel for (family, N, G): one instance per G lanes, n <= N; null when
+// that build does not exist (group.hip).
+lane_launch_fn mt_group_launcher(tron_family fam, int N, int G);

@@ -63,12 +63,10 @@ extern "C" int64_t tron_param_size(tron_family fam, int32_t n)
 // ------------------------------------------------------------------------------------
 constexpr int kLaneBlock = 256;
 
+// Solve instance b in the calling lane.
 template <class F, int N>
-__global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a)
+__device__ __forceinline__ void lane_solve(const LaneArgs &a, int64_t b)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.count) return;
-    const int64_t b = a.index ? (int64_t)a.index[t] : t;
     const int n = a.nper ? a.nper[b] : a.n_uniform;
     const int64_t po = a.poff ? a.poff[b] : b * (int64_t)a.psize;
     const int64_t vo = a.voff ? a.voff[b] : b * (int64_t)n;
@@ -100,6 +98,13 @@ __global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a)
     }
 }
 
+template <class F, int N>
+__global__ __launch_bounds__(kLaneBlock) void lane_kernel(LaneArgs a)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.count) return;
+    lane_solve<F, N>(a, a.index ? (int64_t)a.index[t] : t);
+}
 
 template <class F, int N>
 static void launch_lane(const LaneArgs &a, hipStream_t st)
@@ -212,25 +217,24 @@ __global__ __launch_bounds__(kLaneBlock) void al_kernel(LaneArgs a, AlArgs al)
 // wavefront-per-instance kernels (8 < n <= 128; QP4 and HS45M); one 64-lane workgroup per
 // instance, so the hardware dispatcher hands the next instance to whichever CU frees up first
 // ------------------------------------------------------------------------------------
+// Solve instance b on one wavefront with its matrix array at M (scr: the LDS scratch of the
+// global-memory form, unused otherwise).
 template <class Fam, bool kGlobal>
-__device__ __forceinline__ void wave_body(const LaneArgs &a)
+__device__ __forceinline__ void wave_solve(const LaneArgs &a, int64_t b, double *M, double *scr)
 {
-    extern __shared__ double smem[];
-    const int64_t t = blockIdx.x;
-    if (t >= a.count) return;
-    const int64_t b = a.index ? (int64_t)a.index[t] : t;
     const int n = a.nper ? a.nper[b] : a.n_uniform;
     const int64_t po = a.poff ? a.poff[b] : b * (int64_t)a.psize;
     const int64_t vo = a.voff ? a.voff[b] : b * (int64_t)n;
     const int64_t t0 = a.ts ? (int64_t)wall_clock64() : 0;
     constexpr int R = Fam::R;
+    const int lane = threadIdx.x & 63;
     mt::WaveTron<Fam, kGlobal> s;
     s.n = n;
     s.ld = (n + 1) | 1;  // odd and > n: column n holds the factor's pivots
-    s.lane = threadIdx.x;
-    s.M = kGlobal ? a.ws + t * a.ws_stride : smem;
-    s.P = kGlobal ? smem : nullptr;
-    s.Q = kGlobal ? smem + 16 * 17 : nullptr;
+    s.lane = lane;
+    s.M = M;
+    s.P = kGlobal ? scr : nullptr;
+    s.Q = kGlobal ? scr + 16 * 17 : nullptr;
     s.load(a.params + po, a.lo + vo, a.hi + vo, a.x0 + vo);
     const double din = a.opt.warm ? a.state[b] : 0.0;
     const double ain = a.opt.warm ? a.state[a.batch + b] : 0.0;
@@ -238,7 +242,7 @@ __device__ __forceinline__ void wave_body(const LaneArgs &a)
     double *xo = a.x + vo;
     MT_UNROLL for (int r = 0; r < R; r++)
         if (s.valid(r)) xo[s.row(r)] = s.x[r];
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
         a.f[b] = s.f;
         a.status[b] = st;
         a.iters[b] = s.iters;
@@ -249,6 +253,16 @@ __device__ __forceinline__ void wave_body(const LaneArgs &a)
             a.ts[2 * b + 1] = (int64_t)wall_clock64();
         }
     }
+}
+
+template <class Fam, bool kGlobal>
+__device__ __forceinline__ void wave_body(const LaneArgs &a)
+{
+    extern __shared__ double smem[];
+    const int64_t t = blockIdx.x;
+    if (t >= a.count) return;
+    const int64_t b = a.index ? (int64_t)a.index[t] : t;
+    wave_solve<Fam, kGlobal>(a, b, kGlobal ? a.ws + t * a.ws_stride : smem, smem);
 }
 
 // Two builds of the same solver. Buckets of small n fit many instances per CU, so their
@@ -337,6 +351,192 @@ static void launch_wave_fam(tron_family fam, const LaneArgs &a, int nmax, hipStr
 static bool has_wave_kernel(tron_family fam) { return fam == TRON_FAMILY_QP4 || fam == TRON_FAMILY_HS45M; }
 
 // ------------------------------------------------------------------------------------
+// persistent size-bucketed launch: one launch for every wavefront instance of a mixed batch
+// ------------------------------------------------------------------------------------
+// A workgroup of kWaves wavefronts owns one CU's LDS as a pool of kPoolPage-byte pages. Each
+// wave loops on its own: claim the next instance of the batch's list (ordered largest n
+// first, so the costliest start first and the cheapest fill in at the end), reserve the
+// instance's matrix array (n ((n+1)|1) doubles) in the pool, solve it, release the pages.
+// Instances of every size thus run side by side on every CU, packed by their actual LDS
+// need, with no bucket waiting for a stream or a hardware queue.
+constexpr int kPoolPage = 512;
+constexpr int kPoolMaxPages = 320;  // 160 KB
+constexpr int kPoolWords = kPoolMaxPages / 32;
+
+struct PoolArgs {
+    int32_t *counter;  // next list position to claim (set to 0 before each launch)
+    int32_t pages;     // pool pages (the launch's dynamic LDS is pages x kPoolPage bytes)
+};
+
+struct PoolCtl {
+    int lock;                    // held while a wave searches the page map
+    uint32_t used[kPoolWords];   // page map; bits set and cleared by atomics
+};
+
+MT_INLINE uint32_t page_bits(int w, int first, int count)
+{
+    const int a0 = first > 32 * w ? first : 32 * w;
+    const int a1 = first + count < 32 * w + 32 ? first + count : 32 * w + 32;
+    if (a0 >= a1) return 0u;
+    const int len = a1 - a0;
+    return (len == 32 ? 0xFFFFFFFFu : ((1u << len) - 1u)) << (a0 - 32 * w);
+}
+
+// Reserve `need` consecutive free pages of the pool (wave-uniform result): lane 0 takes the
+// lock, every lane tests the starts lane, lane + 64, ... against a snapshot of the map, the
+// lowest start that fits is taken. Frees only clear bits, so a snapshot never offers a page
+// that is in use. When nothing fits, the wave sleeps and retries: pages are only held by
+// waves that are solving, and every solve ends.
+MT_INLINE int pool_alloc(PoolCtl &ctl, int total, int need, int lane)
+{
+    for (;;) {
+        int got = 0;
+        if (lane == 0) got = atomicCAS(&ctl.lock, 0, 1) == 0;
+        got = __builtin_amdgcn_readfirstlane(got);
+        if (got) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            uint32_t u[kPoolWords];
+            MT_UNROLL for (int w = 0; w < kPoolWords; w++) u[w] = __atomic_load_n(&ctl.used[w], __ATOMIC_RELAXED);
+            int start = -1;
+            for (int p0 = 0; p0 < total; p0 += 64) {
+                const int p = p0 + lane;
+                bool ok = p + need <= total;
+                MT_UNROLL for (int w = 0; w < kPoolWords; w++) ok = ok && (u[w] & page_bits(w, p, need)) == 0u;
+                const uint64_t bal = __ballot(ok);
+                if (bal) {
+                    start = p0 + (int)__builtin_ctzll(bal);
+                    break;
+                }
+            }
+            start = __builtin_amdgcn_readfirstlane(start);
+            if (start >= 0 && lane == 0)
+                MT_UNROLL for (int w = 0; w < kPoolWords; w++) {
+                    const uint32_t m = page_bits(w, start, need);
+                    if (m) atomicOr(&ctl.used[w], m);
+                }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0) atomicExch(&ctl.lock, 0);
+            if (start >= 0) return start;
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+}
+
+MT_INLINE void pool_free(PoolCtl &ctl, int first, int need, int lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // the solve's LDS accesses are done
+    if (lane == 0)
+        MT_UNROLL for (int w = 0; w < kPoolWords; w++) {
+            const uint32_t m = page_bits(w, first, need);
+            if (m) atomicAnd(&ctl.used[w], ~m);
+        }
+}
+
+// Fam1: the one-row-per-lane solver (n <= 64); Fam2: two rows per lane (n <= 128), or Fam1
+// again when the batch has no such instance.
+template <class Fam1, class Fam2, int kWaves>
+__global__ __launch_bounds__(64 * kWaves) void pool_kernel(LaneArgs a, PoolArgs p)
+{
+    extern __shared__ double smem[];
+    __shared__ PoolCtl ctl;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x == 0) {
+        ctl.lock = 0;
+        for (int w = 0; w < kPoolWords; w++) ctl.used[w] = 0u;
+    }
+    __syncthreads();
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(p.counter, 1);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= a.count) break;
+        const int64_t b = a.index[item];
+        const int n = a.nper ? a.nper[b] : a.n_uniform;
+        const int need = (int)((mt_wave_matrix_doubles(n) * (int64_t)sizeof(double) + kPoolPage - 1) / kPoolPage);
+        const int first = pool_alloc(ctl, p.pages, need, lane);
+        double *M = smem + (size_t)first * (kPoolPage / sizeof(double));
+        if (Fam2::R > 1 && n > 64) wave_solve<Fam2, false>(a, b, M, nullptr);
+        else wave_solve<Fam1, false>(a, b, M, nullptr);
+        pool_free(ctl, first, need, lane);
+    }
+}
+
+__global__ void pool_reset_kernel(int32_t *counter) { *counter = 0; }
+
+// The persistent launch: one workgroup per CU (the pool takes the CU's LDS), kWaves waves
+// each. `pages` pool pages; nmax the batch's largest wave instance.
+template <template <int> class FamT, int kWaves>
+static void launch_pool_t(const LaneArgs &a, const PoolArgs &p, int nmax, int cus, hipStream_t st)
+{
+    const size_t lds = (size_t)p.pages * kPoolPage;
+    if (nmax > 64)
+        hipLaunchKernelGGL((pool_kernel<FamT<1>, FamT<2>, kWaves>), dim3(cus), dim3(64 * kWaves), lds, st, a, p);
+    else
+        hipLaunchKernelGGL((pool_kernel<FamT<1>, FamT<1>, kWaves>), dim3(cus), dim3(64 * kWaves), lds, st, a, p);
+}
+
+static void launch_pool(tron_family fam, const LaneArgs &a, const PoolArgs &p, int nmax, int waves, int cus,
+                        hipStream_t st)
+{
+    using namespace mt;
+    if (a.count <= 0) return;
+    hipLaunchKernelGGL(pool_reset_kernel, dim3(1), dim3(1), 0, st, p.counter);
+    if (fam == TRON_FAMILY_HS45M) {
+        if (waves == 12) launch_pool_t<WaveFamHS45M, 12>(a, p, nmax, cus, st);
+        else launch_pool_t<WaveFamHS45M, 8>(a, p, nmax, cus, st);
+    } else {
+        if (waves == 12) launch_pool_t<WaveFamQP4, 12>(a, p, nmax, cus, st);
+        else launch_pool_t<WaveFamQP4, 8>(a, p, nmax, cus, st);
+    }
+}
+
+// The pool kernels may take the whole LDS of a CU (once per process and device).
+static void prepare_pool_kernels(int bytes)
+{
+    using namespace mt;
+    const void *k[] = {(const void *)pool_kernel<WaveFamQP4<1>, WaveFamQP4<1>, 8>,
+                       (const void *)pool_kernel<WaveFamQP4<1>, WaveFamQP4<2>, 8>,
+                       (const void *)pool_kernel<WaveFamQP4<1>, WaveFamQP4<1>, 12>,
+                       (const void *)pool_kernel<WaveFamQP4<1>, WaveFamQP4<2>, 12>,
+                       (const void *)pool_kernel<WaveFamHS45M<1>, WaveFamHS45M<1>, 8>,
+                       (const void *)pool_kernel<WaveFamHS45M<1>, WaveFamHS45M<2>, 8>,
+                       (const void *)pool_kernel<WaveFamHS45M<1>, WaveFamHS45M<1>, 12>,
+                       (const void *)pool_kernel<WaveFamHS45M<1>, WaveFamHS45M<2>, 12>};
+    for (const void *f : k) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+// Lane packs: the instances with n <= 8 in packs of 64 of one size (a wave each; -1 pads a
+// pack), every size in one launch. pack_n[k] is the size of pack k.
+template <template <int> class FamT>
+__global__ __launch_bounds__(64) void lane_pack_kernel(LaneArgs a, const int32_t *pack_n)
+{
+    const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int32_t b = a.index[t];
+    if (b < 0) return;
+    switch (pack_n[blockIdx.x]) {
+    case 1: lane_solve<FamT<1>, 1>(a, b); break;
+    case 2: lane_solve<FamT<2>, 2>(a, b); break;
+    case 3: lane_solve<FamT<3>, 3>(a, b); break;
+    case 4: lane_solve<FamT<4>, 4>(a, b); break;
+    case 5: lane_solve<FamT<5>, 5>(a, b); break;
+    case 6: lane_solve<FamT<6>, 6>(a, b); break;
+    case 7: lane_solve<FamT<7>, 7>(a, b); break;
+    default: lane_solve<FamT<8>, 8>(a, b); break;
+    }
+}
+
+static void launch_lane_packs(tron_family fam, const LaneArgs &a, const int32_t *pack_n, int64_t packs,
+                              hipStream_t st)
+{
+    using namespace mt;
+    if (packs <= 0) return;
+    if (fam == TRON_FAMILY_HS45M)
+        hipLaunchKernelGGL(lane_pack_kernel<HS45M>, dim3((unsigned)packs), dim3(64), 0, st, a, pack_n);
+    else
+        hipLaunchKernelGGL(lane_pack_kernel<QP4>, dim3((unsigned)packs), dim3(64), 0, st, a, pack_n);
+}
+
+// ------------------------------------------------------------------------------------
 // batch handle
 // ------------------------------------------------------------------------------------
 struct Bucket {
@@ -371,7 +571,7 @@ void mt_prepare_wave_kernels()
 
 static void launch_bucket(tron_family fam, const Bucket &b, const LaneArgs &a0, hipStream_t st)
 {
-    if (b.lanes == 1) {
+    if (b.lanes < 64) {
         b.lane(a0, st);
         return;
     }
@@ -394,12 +594,18 @@ static void default_spec(tron_plan_spec *p)
     for (int i = 0; i < 16; i++) p->edges[i] = i < kN ? e[i] : 0;
     p->streams = kMaxSideStreams;
     p->lane_block = 64;
+    p->pool_waves = 0;
+    p->lane_group = 1;
+    p->group16 = 0;
 }
 
 static tron_err check_spec(const tron_plan_spec &p)
 {
     if (p.lane_max_n < 0 || p.lane_max_n > 8 || p.nedges < 1 || p.nedges > 16 || p.streams < 1 ||
-        p.streams > 8 || (p.lane_block != 64 && p.lane_block != 256))
+        p.streams > 8 || (p.lane_block != 64 && p.lane_block != 256) ||
+        (p.pool_waves != 0 && p.pool_waves != 8 && p.pool_waves != 12) ||
+        (p.lane_group != 1 && p.lane_group != 2 && p.lane_group != 4 && p.lane_group != 8) ||
+        (p.group16 != 0 && p.group16 != 8 && p.group16 != 16))
         return mt_fail(TRON_ERR_INVALID, "invalid plan spec");
     for (int i = 0; i < p.nedges; i++)
         if (p.edges[i] < 1 || p.edges[i] > 128 || (i > 0 && p.edges[i] <= p.edges[i - 1]))
@@ -436,6 +642,14 @@ struct tron_batch {
     hipGraphExec_t graph = nullptr;
     hipStream_t cap = nullptr;           // capture stream
     const void *graph_key[9] = {};
+    // persistent form (spec.pool_waves > 0 on a mixed batch): the wavefront instances ordered
+    // largest n first, their claim counter, and the lane instances in packs of 64 of one size
+    bool pool = false;
+    int64_t pool_count = 0, packs = 0;
+    int32_t pool_nmax = 0, pool_pages = 0, cus = 0;
+    int32_t *d_pool_index = nullptr, *d_counter = nullptr;
+    int32_t *d_pack_index = nullptr, *d_pack_n = nullptr;
+    std::vector<int64_t> pack_count;     // instances per lane size (1..8), for tron_batch_plan
 };
 
 static void drop_graph(tron_batch *h)
@@ -467,6 +681,10 @@ static void free_batch(tron_batch *h)
     (void)hipFree(h->d_n);
     (void)hipFree(h->d_poff);
     (void)hipFree(h->d_voff);
+    (void)hipFree(h->d_pool_index);
+    (void)hipFree(h->d_counter);
+    (void)hipFree(h->d_pack_index);
+    (void)hipFree(h->d_pack_n);
     for (auto &b : h->buckets) {
         (void)hipFree(b.d_index);
         (void)hipFree(b.d_ws);
@@ -478,6 +696,88 @@ static tron_err check_options(const tron_options &o)
 {
     if (!(o.gtol >= 0.0) || o.max_iter < 0 || !(o.cg_rtol >= 0.0) || !(o.delta0 == o.delta0))
         return mt_fail(TRON_ERR_INVALID, "invalid options");
+    return TRON_OK;
+}
+
+// The kernel of a bucket of instances of size n <= lane_max_n under the spec: the lane kernel
+// of exactly that n, or the group kernel of width lane_group (null when the family has no
+// such build); `lanes` receives the lanes per instance.
+static lane_launch_fn small_launcher(tron_family fam, const tron_plan_spec &sp, int n, int *lanes)
+{
+    if (sp.lane_group > 1) {
+        const int kn = fam == TRON_FAMILY_BR6 ? 6 : 8;
+        lane_launch_fn f = n <= kn ? mt_group_launcher(fam, kn, sp.lane_group) : nullptr;
+        if (f) {
+            *lanes = sp.lane_group;
+            return f;
+        }
+    }
+    *lanes = 1;
+    return lane_launcher(fam, n);
+}
+
+// The group kernel for lane_max_n < n <= 16 when the spec asks for one (else null).
+static lane_launch_fn mid_launcher(tron_family fam, const tron_plan_spec &sp, int n)
+{
+    if (sp.group16 == 0 || n > 16 || n <= sp.lane_max_n) return nullptr;
+    return mt_group_launcher(fam, 16, sp.group16);
+}
+
+// The persistent form: the wavefront instances ordered largest n first (the costliest start
+// first; within one n, instance order), and the lane instances grouped by size into packs of
+// 64 (the last pack of a size padded with -1).
+static tron_err build_pool_plan(tron_batch *h, const std::vector<int32_t> &n, hipStream_t st)
+{
+    const tron_plan_spec &sp = h->spec;
+    std::vector<int32_t> wave;
+    std::vector<std::vector<int32_t>> lanes(9);
+    for (int64_t i = 0; i < h->batch; i++) {
+        const bool lane = n[i] <= sp.lane_max_n && lane_launcher(h->fam, n[i]) != nullptr;
+        if (lane) lanes[n[i]].push_back((int32_t)i);
+        else {
+            if (!has_wave_kernel(h->fam)) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d has no kernel for this family", n[i]);
+            wave.push_back((int32_t)i);
+        }
+    }
+    std::stable_sort(wave.begin(), wave.end(), [&](int32_t a, int32_t b) { return n[a] > n[b]; });
+    std::vector<int32_t> pidx, pn;
+    h->pack_count.assign(9, 0);
+    for (int k = 8; k >= 1; k--) {
+        const auto &l = lanes[k];
+        h->pack_count[k] = (int64_t)l.size();
+        for (size_t i = 0; i < l.size(); i += 64) {
+            for (size_t j = 0; j < 64; j++) pidx.push_back(i + j < l.size() ? l[i + j] : -1);
+            pn.push_back(k);
+        }
+    }
+    int dev = 0, cus = 0, lds = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIP_TRY(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    h->pool = true;
+    h->cus = cus;
+    // the pool takes what a workgroup may have, less the pool's own control block
+    h->pool_pages = std::min(kPoolMaxPages, (int)((lds - (int)sizeof(PoolCtl)) / kPoolPage));
+    h->pool_count = (int64_t)wave.size();
+    h->packs = (int64_t)pn.size();
+    h->pool_nmax = 0;
+    for (int32_t i : wave) h->pool_nmax = std::max(h->pool_nmax, n[i]);
+    if (h->pool_nmax > 0 &&
+        (int64_t)h->pool_pages * kPoolPage < mt_wave_matrix_doubles(h->pool_nmax) * (int64_t)sizeof(double))
+        return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d does not fit the LDS pool", h->pool_nmax);
+    HIP_TRY(hipMalloc(&h->d_counter, sizeof(int32_t)));
+    if (!wave.empty()) {
+        HIP_TRY(hipMalloc(&h->d_pool_index, sizeof(int32_t) * wave.size()));
+        HIP_TRY(hipMemcpyAsync(h->d_pool_index, wave.data(), sizeof(int32_t) * wave.size(), hipMemcpyHostToDevice, st));
+    }
+    if (!pn.empty()) {
+        HIP_TRY(hipMalloc(&h->d_pack_index, sizeof(int32_t) * pidx.size()));
+        HIP_TRY(hipMalloc(&h->d_pack_n, sizeof(int32_t) * pn.size()));
+        HIP_TRY(hipMemcpyAsync(h->d_pack_index, pidx.data(), sizeof(int32_t) * pidx.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(h->d_pack_n, pn.data(), sizeof(int32_t) * pn.size(), hipMemcpyHostToDevice, st));
+    }
+    prepare_pool_kernels(h->pool_pages * kPoolPage);
+    HIP_TRY(hipStreamSynchronize(st));
     return TRON_OK;
 }
 
@@ -498,8 +798,11 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
         b.d_index = nullptr;
         if (lane_ok(h->n_uniform)) {
             b.nmax = h->n_uniform;
-            b.lanes = 1;
-            b.lane = lane_launcher(h->fam, h->n_uniform);
+            b.lane = small_launcher(h->fam, sp, h->n_uniform, &b.lanes);
+        } else if (lane_launch_fn m = mid_launcher(h->fam, sp, h->n_uniform)) {
+            b.nmax = 16;
+            b.lanes = sp.group16;
+            b.lane = m;
         } else {
             if (!has_wave_kernel(h->fam)) return mt_fail(TRON_ERR_UNSUPPORTED, "this family has no wave kernel");
             b.nmax = h->n_uniform;
@@ -512,10 +815,17 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
         h->buckets.push_back(b);
         return TRON_OK;
     }
+    if (sp.pool_waves > 0) {
+        int nmax = 0;
+        for (int64_t i = 0; i < h->batch; i++) nmax = std::max(nmax, n[i]);
+        if (nmax <= kLdsMaxN) return build_pool_plan(h, n, st);
+    }
     std::vector<std::vector<int32_t>> lane_lists(9);
+    std::vector<int32_t> mid_list;                   // lane_max_n < n <= 16 on the group kernel
     std::map<int, std::vector<int32_t>> wave_lists;  // edge -> instances
     for (int64_t i = 0; i < h->batch; i++) {
         if (lane_ok(n[i])) lane_lists[n[i]].push_back((int32_t)i);
+        else if (mid_launcher(h->fam, sp, n[i])) mid_list.push_back((int32_t)i);
         else {
             if (!has_wave_kernel(h->fam)) return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d has no kernel for this family", n[i]);
             const int e = n[i] > kLdsMaxN ? global_edge(n[i]) : spec_edge(sp, n[i]);
@@ -523,14 +833,15 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
             wave_lists[e].push_back((int32_t)i);
         }
     }
-    auto add = [&](std::vector<int32_t> &list, int nmax, int lanes) -> tron_err {
+    // lanes: 64 for the wavefront kernel, else the lanes per instance of `fn`
+    auto add = [&](std::vector<int32_t> &list, int nmax, int lanes, lane_launch_fn fn) -> tron_err {
         // registered first, so that free_batch releases whatever the allocations below got
         h->buckets.push_back(Bucket{});
         Bucket &b = h->buckets.back();
         b.nmax = nmax;
         b.lanes = lanes;
         b.count = (int64_t)list.size();
-        b.lane = lanes == 1 ? lane_launcher(h->fam, nmax) : nullptr;
+        b.lane = fn;
         if (lanes == 64 && nmax > kLdsMaxN &&
             hipMalloc(&b.d_ws, sizeof(double) * (size_t)mt_wave_matrix_doubles(nmax) * list.size()) != hipSuccess)
             return mt_fail(TRON_ERR_NOMEM, "matrix workspace allocation failed");
@@ -541,12 +852,19 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
     for (auto it = wave_lists.rbegin(); it != wave_lists.rend(); ++it) {
         auto &list = it->second;
         std::stable_sort(list.begin(), list.end(), [&](int32_t a, int32_t b) { return n[a] > n[b]; });
-        tron_err rc = add(list, it->first, 64);
+        tron_err rc = add(list, it->first, 64, nullptr);
+        if (rc != TRON_OK) return rc;
+    }
+    if (!mid_list.empty()) {
+        std::stable_sort(mid_list.begin(), mid_list.end(), [&](int32_t a, int32_t b) { return n[a] > n[b]; });
+        tron_err rc = add(mid_list, 16, sp.group16, mid_launcher(h->fam, sp, n[mid_list[0]]));
         if (rc != TRON_OK) return rc;
     }
     for (int k = 8; k >= 1; k--) {
         if (lane_lists[k].empty()) continue;
-        tron_err rc = add(lane_lists[k], k, 1);
+        int lanes = 1;
+        lane_launch_fn fn = small_launcher(h->fam, sp, k, &lanes);
+        tron_err rc = add(lane_lists[k], k, lanes, fn);
         if (rc != TRON_OK) return rc;
     }
     // the device copies above read host vectors that die with this call
@@ -646,8 +964,9 @@ extern "C" tron_err tron_batch_create_ex(tron_batch **out, tron_family fam, int6
     }
     rc = build_plan(h, n, st);
     if (rc != TRON_OK) return bail(rc);
-    if (h->buckets.size() > 1 && sp.streams > 1) {
-        const int k = (int)std::min<size_t>(h->buckets.size(), (size_t)sp.streams);
+    const size_t parts = h->pool ? (size_t)((h->pool_count > 0) + (h->packs > 0)) : h->buckets.size();
+    if (parts > 1 && (h->pool || sp.streams > 1)) {
+        const int k = h->pool ? 2 : (int)std::min<size_t>(h->buckets.size(), (size_t)sp.streams);
         for (int i = 0; i < k; i++) {
             hipStream_t q;
             if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess)
@@ -712,7 +1031,33 @@ extern "C" tron_err tron_batch_solve(tron_batch *h, const double *d_params, cons
         HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     }
     tron_err rc = TRON_OK;
-    if (h->side.empty()) {
+    if (h->pool) {
+        // the lane packs and the persistent launch, side by side when both exist
+        LaneArgs ap = a, al = a;
+        ap.index = h->d_pool_index;
+        ap.count = h->pool_count;
+        al.index = h->d_pack_index;
+        al.count = h->packs * 64;
+        const PoolArgs pa{h->d_counter, h->pool_pages};
+        const int waves = h->spec.pool_waves;
+        if (h->side.empty()) {
+            launch_pool(h->fam, ap, pa, h->pool_nmax, waves, h->cus, cs);
+            launch_lane_packs(h->fam, al, h->d_pack_n, h->packs, cs);
+        } else {
+            if (hipEventRecord(h->ev[0], cs) != hipSuccess) rc = mt_fail(TRON_ERR_DEVICE, "event record failed");
+            for (int i = 0; i < 2 && rc == TRON_OK; i++)
+                if (hipStreamWaitEvent(h->side[i], h->ev[0], 0) != hipSuccess)
+                    rc = mt_fail(TRON_ERR_DEVICE, "stream wait failed");
+            if (rc == TRON_OK) {
+                launch_pool(h->fam, ap, pa, h->pool_nmax, waves, h->cus, h->side[0]);
+                launch_lane_packs(h->fam, al, h->d_pack_n, h->packs, h->side[1]);
+            }
+            for (int i = 0; i < 2 && rc == TRON_OK; i++)
+                if (hipEventRecord(h->ev[1 + i], h->side[i]) != hipSuccess ||
+                    hipStreamWaitEvent(cs, h->ev[1 + i], 0) != hipSuccess)
+                    rc = mt_fail(TRON_ERR_DEVICE, "join failed");
+        }
+    } else if (h->side.empty()) {
         for (const Bucket &b : h->buckets) {
             a.index = b.d_index;
             a.count = b.count;
@@ -838,6 +1183,18 @@ extern "C" tron_err tron_batch_plan(const tron_batch *h, int32_t *nbuckets, int3
                                     int32_t max_buckets)
 {
     if (!h || !nbuckets) return mt_fail(TRON_ERR_INVALID, "null argument");
+    if (h->pool) {
+        // the persistent launch as one entry (largest n, 64 lanes, its instances), then one
+        // entry per lane size
+        std::vector<int32_t> d;
+        if (h->pool_count) d.insert(d.end(), {h->pool_nmax, 64, (int32_t)h->pool_count});
+        for (int k = 8; k >= 1; k--)
+            if (h->pack_count.size() > (size_t)k && h->pack_count[k]) d.insert(d.end(), {k, 1, (int32_t)h->pack_count[k]});
+        *nbuckets = (int32_t)(d.size() / 3);
+        for (int32_t i = 0; desc && i < max_buckets && i < *nbuckets; i++)
+            for (int c = 0; c < 3; c++) desc[3 * i + c] = d[3 * i + c];
+        return TRON_OK;
+    }
     *nbuckets = (int32_t)h->buckets.size();
     for (int32_t i = 0; desc && i < max_buckets && i < (int32_t)h->buckets.size(); i++) {
         desc[3 * i] = h->buckets[i].nmax;
@@ -892,6 +1249,7 @@ static std::string spec_str(const tron_plan_spec &p)
     std::ostringstream o;
     o << p.lane_max_n << " " << p.streams << " " << p.lane_block << " " << p.nedges;
     for (int i = 0; i < p.nedges; i++) o << " " << p.edges[i];
+    o << " " << p.pool_waves << " " << p.lane_group << " " << p.group16;
     return o.str();
 }
 
@@ -903,6 +1261,9 @@ static bool spec_parse(const std::string &t, tron_plan_spec *p)
     if (q.nedges < 1 || q.nedges > 16) return false;
     for (int i = 0; i < q.nedges; i++)
         if (!(in >> q.edges[i])) return false;
+    if (!(in >> q.pool_waves)) q.pool_waves = 0;
+    if (!(in >> q.lane_group)) q.lane_group = 1;
+    if (!(in >> q.group16)) q.group16 = 0;
     if (check_spec(q) != TRON_OK) return false;
     *p = q;
     return true;
@@ -987,6 +1348,41 @@ extern "C" tron_err tron_autotune(tron_family fam, int64_t batch, const int32_t 
             if (rc == TRON_OK && ms < cur_ms) { cur_ms = ms; cur = sp; }
         }
     }
+    // stage 3: group widths for the lane sizes and for 8 < n <= 16
+    for (int lg : {2, 4, 8}) {
+        if (rc != TRON_OK) break;
+        tron_plan_spec sp = cur;
+        sp.lane_group = lg;
+        double ms = 0.0;
+        rc = time_spec(sp, &ms);
+        if (rc == TRON_OK && ms < cur_ms) { cur_ms = ms; cur = sp; }
+    }
+    if (has_wave_kernel(fam) && nmax > cur.lane_max_n) {
+        for (int g16 : {8, 16}) {
+            if (rc != TRON_OK) break;
+            tron_plan_spec sp = cur;
+            sp.group16 = g16;
+            double ms = 0.0;
+            rc = time_spec(sp, &ms);
+            if (rc == TRON_OK && ms < cur_ms) { cur_ms = ms; cur = sp; }
+        }
+    }
+    // stage 4: the persistent form (wave instances up to 128 only), with the best lane split
+    // and 0 / 4 / 8 lane sizes
+    if (nmax <= kLdsMaxN && has_wave_kernel(fam)) {
+        for (int waves : {8, 12}) {
+            for (int lane_max : {cur.lane_max_n, 0}) {
+                if (rc != TRON_OK) break;
+                tron_plan_spec sp = cur;
+                sp.pool_waves = waves;
+                sp.lane_max_n = lane_max;
+                double ms = 0.0;
+                rc = time_spec(sp, &ms);
+                if (rc == TRON_OK && ms < cur_ms) { cur_ms = ms; cur = sp; }
+                if (lane_max == 0 && cur.lane_max_n == 0) break;
+            }
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != TRON_OK) return rc;
@@ -998,3 +1394,4 @@ extern "C" tron_err tron_autotune(tron_family fam, int64_t batch, const int32_t 
     }
     return TRON_OK;
 }
+

@@ -381,3 +381,170 @@ def test_plan_specs_and_autotune(tron, tmp_path):
     assert ms2 == -1.0 and best2.describe() == best.describe()
     h = tron.Batch(W.QP4, sizes, spec=best)
     h.close()
+
+
+# ---------------------------------------------------------------------------------------
+# the persistent size-bucketed launch (plan spec pool_waves 8 or 12)
+# ---------------------------------------------------------------------------------------
+def _solve_spec(T, bt, spec, **kw):
+    import torch
+    h = T.Batch(bt.family, bt.n, spec=spec, opts=T.options(**kw))
+    x, f, st, it = h.solve(*T.to_device(bt))
+    torch.cuda.synchronize()
+    out = dict(x=x.cpu().numpy(), f=f.cpu().numpy(), status=st.cpu().numpy(), iters=it.cpu().numpy())
+    plan = h.plan()
+    h.close()
+    return out, plan
+
+
+@pytest.mark.parametrize("waves", [8, 12])
+def test_pool_plan_uneven_full_size(tron, waves):
+    """The uneven benchmark's batch (50,000 quartic problems, n log-uniform in [4,64]) through
+    the persistent launch, captured in a graph and replayed: every instance against the
+    oracle, and the same bits as the bucketed plan (the same solver code runs each
+    instance; only where it runs differs)."""
+    sizes, bt, dev, out = _uneven_setup(tron)
+    ref = oracle_ref(bt)
+    g = _run_plan(tron, sizes, dev, out, spec=tron.plan_spec(pool_waves=waves))
+    assert np.all(g["status"] == 0)
+    check_parity(bt, g, ref, convex=True, label=f"uneven 50000, persistent {waves} waves")
+    b = _run_plan(tron, sizes, dev, out)
+    for k in ("x", "f", "status", "iters"):
+        assert np.array_equal(g[k], b[k]), k
+
+
+@pytest.mark.parametrize("fam", ["qp4", "hs45m"])
+def test_pool_plan_mixed_to_128(tron, fam):
+    """Sizes 1..128 in one persistent launch (one and two rows per lane in the same kernel),
+    with every lane size in the lane packs, against the oracle."""
+    sizes = W.loguniform_sizes(700, 1, 128, config_id=36)
+    bt = W.qp4_batch(700, sizes, config_id=36) if fam == "qp4" else W.hs45m_random_start(700, sizes, config_id=36)
+    ref = oracle_ref(bt)
+    for waves in (8, 12):
+        g, plan = _solve_spec(tron, bt, tron.plan_spec(pool_waves=waves))
+        assert plan[0]["lanes"] == 64 and plan[0]["nmax"] == int(sizes.max())
+        assert sum(p["count"] for p in plan) == 700
+        check_parity(bt, g, ref, convex=(fam == "qp4"), label=f"pool {fam} {waves} waves, n to 128")
+        if fam == "hs45m":
+            assert np.array_equal(g["x"], bt.hi)  # the global minimiser, the upper corner
+
+
+def test_pool_plan_partitions(tron):
+    """Every instance in the persistent launch (lane_max_n 0, sizes from 1), every instance in
+    the lane packs (all n <= 8), and a tiny batch with fewer wave instances than CUs."""
+    sizes = W.loguniform_sizes(500, 1, 40, config_id=37)
+    bt = W.qp4_batch(500, sizes, config_id=37)
+    ref = oracle_ref(bt)
+    g, plan = _solve_spec(tron, bt, tron.plan_spec(lane_max_n=0, pool_waves=8))
+    assert len(plan) == 1 and plan[0]["count"] == 500
+    check_parity(bt, g, ref, convex=True, label="pool, no lane packs")
+    small = W.qp4_batch(300, W.loguniform_sizes(300, 1, 8, config_id=38), config_id=38)
+    g, plan = _solve_spec(tron, small, tron.plan_spec(pool_waves=12))
+    assert all(p["lanes"] == 1 for p in plan)
+    check_parity(small, g, oracle_ref(small), convex=True, label="lane packs only")
+    few = W.qp4_batch(7, np.array([9, 64, 33, 2, 17, 50, 12], dtype=np.int32), config_id=39)
+    g, _ = _solve_spec(tron, few, tron.plan_spec(pool_waves=8))
+    check_parity(few, g, oracle_ref(few), convex=True, label="pool, 7 instances")
+
+
+def test_pool_graph_replays_and_warm(tron):
+    """Graph replays of the persistent launch (its claim counter is reset inside the graph)
+    give the eager bits every time; warm starts read the resident state it wrote."""
+    import torch
+    sizes = W.loguniform_sizes(900, 2, 72, config_id=34)
+    bt = W.qp4_batch(900, sizes, config_id=34)
+    dev = tron.to_device(bt)
+    spec = tron.plan_spec(pool_waves=8)
+    eager = tron.Batch(W.QP4, sizes, spec=spec)
+    xe, fe, se, ie = [t.clone() for t in eager.solve(*dev)]
+    torch.cuda.synchronize()
+    g = tron.Batch(W.QP4, sizes, spec=spec, opts=tron.options(graph=True))
+    x = torch.empty_like(xe); f = torch.empty_like(fe)
+    st = torch.empty_like(se); it = torch.empty_like(ie)
+    for rep in range(4):
+        x.fill_(-7.0); f.zero_(); st.fill_(-1); it.fill_(-1)
+        g.solve(*dev, x=x, f=f, status=st, iters=it)
+        torch.cuda.synchronize()
+        assert torch.equal(x, xe) and torch.equal(f, fe) and torch.equal(st, se) and torch.equal(it, ie), rep
+        eager.solve(*dev)
+        _ = (x * 2).sum().item()
+        torch.cuda.synchronize()
+    g.close()
+    # warm restart from the solution: every instance converges at once with the stored radius
+    w = tron.Batch(W.QP4, sizes, spec=spec)
+    x1, _, _, _ = w.solve(*dev)
+    w.set_options(tron.options(warm=True))
+    p, lo, hi, _ = dev
+    x2, _, s2, i2 = w.solve(p, lo, hi, x1.clone())
+    torch.cuda.synchronize()
+    assert int((s2 == 0).sum()) == 900 and int(i2.max()) == 0
+    w.close()
+    eager.close()
+
+
+# ---------------------------------------------------------------------------------------
+# the group kernel: one instance per group of G lanes (plan spec lane_group / group16)
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("g", [2, 4, 8])
+def test_group_kernel_lane_sizes(tron, g):
+    """n <= 8 on groups of 2, 4 or 8 lanes: QP4 at every n (padded rows inside a group),
+    the branch batch with a ragged tail, and HS45M from random starts, against the oracle."""
+    spec = tron.plan_spec(lane_group=g)
+    for n in (1, 3, 6, 8):
+        bt = W.qp4_batch(257, n, config_id=110 + n)
+        out, plan = _solve_spec(tron, bt, spec)
+        assert plan[0]["lanes"] == g
+        check_parity(bt, out, oracle_ref(bt), convex=True, label=f"group {g}, qp4 n={n}")
+    bt = W.br6_batch(4096 + 37, config_id=1)
+    out, plan = _solve_spec(tron, bt, spec)
+    assert plan[0]["lanes"] == g and np.all(out["status"] == 0)
+    check_parity(bt, out, oracle_ref(bt), convex=False, label=f"group {g}, br6")
+    hs = W.hs45m_random_start(300, W.loguniform_sizes(300, 1, 8, config_id=72), config_id=72)
+    out, _ = _solve_spec(tron, hs, spec)
+    check_parity(hs, out, oracle_ref(hs), convex=False, label=f"group {g}, hs45m")
+    assert np.array_equal(out["x"], hs.hi)
+
+
+@pytest.mark.parametrize("g", [8, 16])
+def test_group_kernel_to_16(tron, g):
+    """8 < n <= 16 on groups of 8 or 16 lanes (two or four instances per 16-lane row) in a
+    mixed batch with lane and wavefront sizes around it, and the full-size uneven batch's
+    small instances, against the oracle; the tight-tolerance companion meets the x bar with
+    no allowance."""
+    sizes = W.loguniform_sizes(900, 1, 40, config_id=73)
+    bt = W.qp4_batch(900, sizes, config_id=73)
+    spec = tron.plan_spec(group16=g)
+    out, plan = _solve_spec(tron, bt, spec)
+    mid = [p for p in plan if p["lanes"] == g]
+    assert len(mid) == 1 and mid[0]["count"] == int(((sizes > 8) & (sizes <= 16)).sum())
+    check_parity(bt, out, oracle_ref(bt), convex=True, label=f"group16={g}")
+    out, _ = _solve_spec(tron, bt, spec, gtol=1e-10)
+    check_parity(bt, out, oracle_ref(bt, gtol=1e-10), convex=True, allow_splits=False,
+                 label=f"group16={g}, gtol 1e-10")
+    hs = W.hs45m_random_start(400, W.loguniform_sizes(400, 9, 16, config_id=74), config_id=74)
+    out, _ = _solve_spec(tron, hs, spec)
+    check_parity(hs, out, oracle_ref(hs), convex=False, label=f"group16={g}, hs45m")
+    assert np.array_equal(out["x"], hs.hi)
+
+
+def test_group_kernel_edge_cases(tron):
+    """Bad bounds, a NaN start, fixed variables and max_iter = 1 on the group kernels give
+    the oracle's statuses, and an instance's result does not depend on its group neighbours
+    (the same instance alone and inside a batch, bitwise)."""
+    import torch
+    for spec, n in ((tron.plan_spec(lane_group=4), 6), (tron.plan_spec(group16=16), 12)):
+        bt = W.qp4_batch(6, n, config_id=75)
+        bt.lo[2 * n] = 3.0  # instance 2: l > u
+        bt.x0[3 * n + 1] = np.nan  # instance 3: NaN start
+        bt.lo[4 * n:5 * n] = bt.hi[4 * n:5 * n] = 0.25  # instance 4: every variable fixed
+        out, _ = _solve_spec(tron, bt, spec)
+        ref = oracle_ref(bt)
+        assert np.array_equal(out["status"], ref["status"]), (out["status"], ref["status"])
+        out1, _ = _solve_spec(tron, bt, spec, max_iter=1)
+        ref1 = oracle_ref(bt, max_iter=1)
+        assert np.array_equal(out1["status"] != 0, ref1["status"] != 0)
+        big = W.qp4_batch(64, n, config_id=76)
+        full, _ = _solve_spec(tron, big, spec)
+        one, _ = _solve_spec(tron, big.subset(np.array([37])), spec)
+        vo = big.voff()
+        assert np.array_equal(one["x"], full["x"][vo[37]:vo[38]]) and one["f"][0] == full["f"][37]
