@@ -223,6 +223,27 @@ int64_t tron_clock_rate_hz(void);
 
 tron_err tron_batch_destroy(tron_batch *h);
 
+/* Allocation-free solve, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc). One cold-start
+ * solve of `batch` instances that all have size n, with the same kernels and results as
+ * tron_batch_create(n_uniform = n) + tron_batch_solve: instances with n <= 8 one per GPU
+ * lane, larger ones one per wavefront. The solve's working memory (per-instance radius and
+ * Cauchy step length, 16 bytes each, and for n > 128 the matrix workspace of
+ * n ((n+1)|1) doubles per instance) lives in a fixed device array of the library,
+ * tron_noalloc_scratch_bytes() = 64 MiB on every device the call runs on, held until the
+ * process ends; the call makes no device allocation. The caller passes inputs and outputs
+ * as for tron_batch_solve (d_x0 and d_x may alias). opt may be NULL; its flags must be 0.
+ * The array is shared by every call on a device and keeps the last call's contents (a call
+ * writes every word it reads first), so calls that overlap in time on one device race:
+ * issue them on one stream. Asynchronous on `stream`.
+ * Errors: INVALID (bad family/n/batch, nonzero flags, null pointers, or a batch whose
+ * working memory exceeds the array), UNSUPPORTED (device index above 63), DEVICE. */
+tron_err tron_solve_noalloc(tron_family family, int64_t batch, int32_t n, const tron_options *opt,
+                            const double *d_params, const double *d_lo, const double *d_hi,
+                            const double *d_x0, double *d_x, double *d_f, int32_t *d_status,
+                            int32_t *d_iters, void *stream);
+int64_t tron_noalloc_scratch_bytes(void);
+
 /* ------------------------------------------------------------------------------------ */
 /* Continuous-batching server. Solve requests (each a batch of instances of one family,   */
 /* sizes mixed, the same Algorithm 1 per instance) are queued from any host thread and    */

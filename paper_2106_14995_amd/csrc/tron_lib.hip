@@ -1395,3 +1395,99 @@ extern "C" tron_err tron_autotune(tron_family fam, int64_t batch, const int32_t 
     return TRON_OK;
 }
 
+// ------------------------------------------------------------------------------------
+// allocation-free solve: the working memory of one uniform-n solve (per-instance radius and
+// Cauchy step length, and for n > 128 the matrix workspace) lives in one fixed device array
+// instead of handle allocations
+// ------------------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+constexpr int kScratchMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[kScratchMaxDevices];  // device address of `scratch`, per device
+
+// The device address of this device's copy of `scratch` (the host-side name is only a
+// stand-in); looked up once per device, with that device current.
+static tron_err scratch_address(double **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kScratchMaxDevices)
+        return mt_fail(TRON_ERR_UNSUPPORTED, "device %d: the allocation-free solve supports devices 0..%d", dev,
+                       kScratchMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return mt_fail(TRON_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        mt_prepare_wave_kernels();
+        g_scratch_dev[dev] = (double *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return TRON_OK;
+}
+
+extern "C" int64_t tron_noalloc_scratch_bytes(void) { return (int64_t)kScratchBytes; }
+
+extern "C" tron_err tron_solve_noalloc(tron_family fam, int64_t batch, int32_t n, const tron_options *opt,
+                                       const double *d_params, const double *d_lo, const double *d_hi,
+                                       const double *d_x0, double *d_x, double *d_f, int32_t *d_status,
+                                       int32_t *d_iters, void *stream)
+{
+    if (fam != TRON_FAMILY_QP4 && fam != TRON_FAMILY_BR6 && fam != TRON_FAMILY_HS45M && fam != TRON_FAMILY_BR8L)
+        return mt_fail(TRON_ERR_INVALID, "unknown family");
+    if (batch < 0 || batch > (int64_t)INT32_MAX) return mt_fail(TRON_ERR_INVALID, "batch out of range");
+    const int64_t psize = tron_param_size(fam, n);
+    if (psize < 0) return mt_fail(TRON_ERR_INVALID, "n = %d invalid for the family", n);
+    tron_options o;
+    tron_default_options(&o);
+    if (opt) o = *opt;
+    if (check_options(o) != TRON_OK) return TRON_ERR_INVALID;
+    if (o.flags != 0u) return mt_fail(TRON_ERR_INVALID, "the allocation-free solve takes no flags (cold start, no graph)");
+    if (batch == 0) return TRON_OK;
+    if ((!d_params && fam != TRON_FAMILY_HS45M) || !d_lo || !d_hi || !d_x0 || !d_x || !d_f || !d_status || !d_iters)
+        return mt_fail(TRON_ERR_INVALID, "null device pointer");
+    const bool lane = n <= 8 && lane_launcher(fam, n) != nullptr;
+    if (!lane && !has_wave_kernel(fam)) return mt_fail(TRON_ERR_UNSUPPORTED, "this family has no wave kernel");
+    // scratch layout: radii [batch], Cauchy steps [batch], then (n > 128) the matrix slots,
+    // 256-byte aligned
+    const int64_t state_doubles = (2 * batch + 31) / 32 * 32;
+    const int64_t ws_stride = (!lane && n > kLdsMaxN) ? mt_wave_matrix_doubles(n) : 0;
+    const int64_t need = state_doubles + ws_stride * batch;
+    if (need > (int64_t)(kScratchBytes / sizeof(double)))
+        return mt_fail(TRON_ERR_INVALID,
+                       "%lld instances of n = %d need %lld bytes of working memory; the allocation-free solve "
+                       "holds %lld",
+                       (long long)batch, n, (long long)(need * (int64_t)sizeof(double)), (long long)kScratchBytes);
+    double *sp = nullptr;
+    tron_err rc = scratch_address(&sp);
+    if (rc != TRON_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    LaneArgs a{};
+    a.params = d_params;
+    a.lo = d_lo;
+    a.hi = d_hi;
+    a.x0 = d_x0;
+    a.x = d_x;
+    a.f = d_f;
+    a.status = d_status;
+    a.iters = d_iters;
+    a.state = sp;  // written, not read (cold start)
+    a.count = batch;
+    a.batch = batch;
+    a.n_uniform = n;
+    a.psize = (int32_t)psize;
+    a.opt = dev_options(o);
+    a.lane_block = 64;
+    if (lane) {
+        lane_launcher(fam, n)(a, st);
+    } else {
+        a.ws = ws_stride ? sp + state_doubles : nullptr;
+        a.ws_stride = ws_stride;
+        launch_wave_fam(fam, a, n, st);
+    }
+    HIP_TRY(hipGetLastError());
+    return TRON_OK;
+}

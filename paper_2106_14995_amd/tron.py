@@ -73,7 +73,8 @@ EXPORTS = ("tron_default_options", "tron_last_error", "tron_param_size", "tron_b
            "tron_server_poll", "tron_server_wait", "tron_server_result", "tron_server_close_session",
            "tron_server_stats", "tron_server_destroy", "tron_batch_set_timestamps", "tron_clock_rate_hz",
            "tron_default_plan_spec", "tron_batch_create_ex", "tron_autotune",
-           "tron_default_al_options", "tron_al_solve", "tron_design_chol", "tron_design_trsv")
+           "tron_default_al_options", "tron_al_solve", "tron_design_chol", "tron_design_trsv",
+           "tron_solve_noalloc", "tron_noalloc_scratch_bytes")
 CHOL_LEFT_LDS, CHOL_RIGHT_LDS, CHOL_LEFT_GLOBAL, CHOL_BLOCKED_MFMA = 0, 1, 2, 3
 TRSV_IMPLICIT, TRSV_PADDED, TRSV_EXPLICIT, TRSV_GLOBAL = 0, 1, 2, 3
 
@@ -131,6 +132,8 @@ def lib():
         L.tron_design_chol.argtypes = [I32, I64, I32, P, P, P, P]
         L.tron_design_trsv.argtypes = [I32, I64, I32, P, P, P, I32, P]
         L.tron_clock_rate_hz.restype = I64
+        L.tron_solve_noalloc.argtypes = [I32, I64, I32, C.POINTER(Options)] + [P] * 9
+        L.tron_noalloc_scratch_bytes.restype = I64
         L.tron_batch_set_timestamps.argtypes = [P, P]
         L.tron_server_default_config.argtypes = [C.POINTER(ServerConfig)]
         L.tron_server_create.argtypes = [C.POINTER(P), I32, C.POINTER(ServerConfig)]
@@ -294,6 +297,33 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def solve_noalloc(family, n, batch, params, lo, hi, x0, x=None, f=None, status=None, iters=None,
+                  opts: Options | None = None, stream=None):
+    """tron_solve_noalloc: one cold-start solve of `batch` instances of uniform size n whose
+    working memory is the library's fixed device array (no device allocation in the call).
+    Outputs not passed in are allocated here by torch."""
+    import torch
+    dev = lo.device
+    nsum = int(batch) * int(n)
+    f64, i32 = torch.float64, torch.int32
+    if x is None:
+        x = torch.empty(nsum, dtype=f64, device=dev)
+    if f is None:
+        f = torch.empty(batch, dtype=f64, device=dev)
+    if status is None:
+        status = torch.empty(batch, dtype=i32, device=dev)
+    if iters is None:
+        iters = torch.empty(batch, dtype=i32, device=dev)
+    psum = param_size(family, n) * int(batch)
+    pp = _dev(params, f64, psum, "params") if psum > 0 else C.c_void_p(0)
+    _check(lib().tron_solve_noalloc(int(family), int(batch), int(n), C.byref(opts) if opts is not None else None,
+                                    pp, _dev(lo, f64, nsum, "lo"), _dev(hi, f64, nsum, "hi"),
+                                    _dev(x0, f64, nsum, "x0"), _dev(x, f64, nsum, "x"),
+                                    _dev(f, f64, batch, "f"), _dev(status, i32, batch, "status"),
+                                    _dev(iters, i32, batch, "iters"), _stream_ptr(stream)))
+    return x, f, status, iters
 
 
 def design_chol(variant, a, l=None, info=None, stream=None):
