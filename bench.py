@@ -356,6 +356,53 @@ def bench_design(args):
                                        "(Table 2)"}), flush=True)
 
 
+def bench_groups(args):
+    """The group-width sweep (section 4.2's thread configuration): one instance per G lanes,
+    G = 1 (the lane kernel), 2, 4, 8, 16, or the whole 64-lane wavefront (the wave kernel),
+    on uniform batches of the quartic family, the hs45 variant and the branch batch. Each
+    figure is the time of one solve of the batch (mean of the timed steps)."""
+    import torch
+    from paper_2106_14995_amd import tron
+    from paper_2106_14995_amd import workloads as W
+    stream = torch.cuda.current_stream()
+    rows = []
+
+    def run(label, fam, bt, n, spec):
+        h = tron.Batch(fam, n, batch=bt.batch, spec=spec)
+        dev = tron.to_device(bt)
+        lat, total = time_solves(lambda: h.solve(*dev, stream=stream), args.steps, args.warmup, stream)
+        _, _, st, it = h.solve(*dev, stream=stream)
+        torch.cuda.synchronize()
+        row = {"case": label, "n": n, "batch": bt.batch, "lanes_per_instance": h.plan()[0]["lanes"],
+               "ms_per_batch": 1e3 * total / args.steps, "converged": int((st == 0).sum().item()),
+               "iters_max": int(it.max().item())}
+        h.close()
+        rows.append(row)
+        log(f"{label} n={n} G={row['lanes_per_instance']}: {row['ms_per_batch']:.4f} ms")
+
+    br = W.br6_batch(65536, config_id=1)
+    for g in (1, 2, 4, 8):
+        run("br6", W.BR6, br, 6, tron.plan_spec(lane_group=g))
+    for n in (4, 8):
+        bt = W.qp4_batch(16384, n, config_id=120 + n)
+        for g in (1, 2, 4, 8):
+            run("qp4", W.QP4, bt, n, tron.plan_spec(lane_group=g))
+        run("qp4", W.QP4, bt, n, tron.plan_spec(lane_max_n=0))
+    for n in (12, 16):
+        bt = W.qp4_batch(16384, n, config_id=120 + n)
+        for g in (8, 16):
+            run("qp4", W.QP4, bt, n, tron.plan_spec(group16=g))
+        run("qp4", W.QP4, bt, n, tron.plan_spec())
+    for n in (8, 16):
+        bt = W.hs45m_random_start(16384, n, config_id=130 + n)
+        specs = [tron.plan_spec(lane_group=g) for g in (1, 2, 4, 8)] if n <= 8 else \
+            [tron.plan_spec(group16=g) for g in (8, 16)] + [tron.plan_spec()]
+        for sp in specs:
+            run("hs45m_random_start", W.HS45M, bt, n, sp)
+    print(json.dumps({"config": "group-width sweep: uniform batches, one solve per step, gtol 1e-6",
+                      "rows": rows}), flush=True)
+
+
 def bench_serve(args):
     """Serving: requests of B = round(exp(U[0, ln 4096])) quartic problems with n log-uniform
     in [4,128], drawn as slices of a seeded pool. The saturated instance rate is measured with
@@ -443,7 +490,7 @@ def main():
     ap.add_argument("--mode", default="br6", choices=["br6", "copy"],
                     help="copy: a plain device-to-device copy of known size, used to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters")
-    ap.add_argument("--config", default="br6", choices=["br6", "qp4", "uneven", "admm", "serve", "hs45m", "al", "design", "large"],
+    ap.add_argument("--config", default="br6", choices=["br6", "qp4", "uneven", "admm", "serve", "hs45m", "al", "design", "large", "groups"],
                     help="br6: the headline batch (default); qp4: 256 x n=8 quartic problems "
                          "(oracle CPU seconds and GPU time); uneven: 50,000 quartic problems with "
                          "n log-uniform in [4,64], bucketed graph vs one launch per size; admm: "
@@ -451,7 +498,8 @@ def main():
                          "stream of requests of 1-4,096 quartic problems, n log-uniform in [4,128]; "
                          "hs45m: the paper's hs45 variant, 10,000 instances, n = 1..32; al: the "
                          "multiplier loop on branch subproblems with line limits; design: the "
-                         "Cholesky / triangular-solve / workspace variants of section 4")
+                         "Cholesky / triangular-solve / workspace variants of section 4; groups: "
+                         "the group-width sweep (lanes per instance)")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per load level")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -478,7 +526,8 @@ def main():
         return
     if args.config != "br6":
         {"qp4": bench_qp4, "uneven": bench_uneven, "admm": bench_admm, "serve": bench_serve,
-         "hs45m": bench_hs45m, "al": bench_al, "design": bench_design, "large": bench_large}[args.config](args)
+         "hs45m": bench_hs45m, "al": bench_al, "design": bench_design, "large": bench_large,
+         "groups": bench_groups}[args.config](args)
         return
     log(f"generating {args.batch} BR6 instances")
     bt = W.br6_batch(args.batch, config_id=1)
