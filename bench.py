@@ -146,6 +146,10 @@ def bench_uneven(args):
     plans = [("bucketed_streams", None, False), ("bucketed_graph", None, True),
              ("persistent_8_graph", tron.plan_spec(pool_waves=8), True),
              ("persistent_12_graph", tron.plan_spec(pool_waves=12), True)]
+    if args.plan:
+        plans = [p for p in plans if p[0] == args.plan]
+        if not plans:
+            raise SystemExit(f"unknown plan {args.plan}")
     for key, spec, graph in plans:
         h = tron.Batch(W.QP4, sizes, opts=tron.options(graph=graph), spec=spec)
         lat, total = time_solves(lambda: h.solve(*dev, **out, stream=stream), args.steps, args.warmup, stream)
@@ -155,6 +159,9 @@ def bench_uneven(args):
         res[key]["converged"] = int((out["status"] == 0).sum().item())
         log(f"{key}: {res[key]['ms_per_batch']:.3f} ms per batch")
         h.close()
+    if args.plan:  # one plan only (for profiling)
+        print(json.dumps(res), flush=True)
+        return
     # autotuned plan (the C autotuner times candidate edge sets / streams / lane split / the
     # persistent form on this batch), then the same graph-captured timing with the chosen plan
     spec, tune_ms = tron.autotune(W.QP4, sizes, *dev, out["x"], out["f"], out["status"], out["iters"],
@@ -501,6 +508,8 @@ def main():
                          "Cholesky / triangular-solve / workspace variants of section 4; groups: "
                          "the group-width sweep (lanes per instance)")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per load level")
+    ap.add_argument("--plan", default="", help="uneven: time only this plan (bucketed_streams, "
+                    "bucketed_graph, persistent_8_graph, persistent_12_graph), e.g. for profiling")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path here (the instances "

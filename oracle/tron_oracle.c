@@ -752,8 +752,12 @@ enum { CG_CONVERGED = 0, CG_MAXIT = 1, CG_NEGCURV = 2, CG_BOUNDARY = 3 };
 /* Trust-region preconditioned CG (Algorithm 1 CG step; section 3; Steihaug). Solves
  * L^-1 A L^-T s_hat = -L^-1 r within ||s_hat||_2 <= delta (readings S5, S6, S9, S10):
  *   stop after |F| iterations, on negative curvature, at the boundary, or when the
- *   residual drops below cg_rtol times its initial norm. Result in w->sh.            */
-static int pcg(ws_t *w, int m, double delta, double cg_rtol)
+ *   residual drops below cg_rtol times its initial norm. Result in w->sh.
+ * exact (reading S33): the preconditioner needed no shift, so L L^T = A and the
+ *   preconditioned matrix is the identity; section 3 notes that CG then ends after one
+ *   iteration, whose step along p = r_hat has length exactly 1: s_hat = r_hat, or the
+ *   boundary point along it when ||r_hat|| >= delta. That step is taken directly.       */
+static int pcg(ws_t *w, int m, double delta, double cg_rtol, int exact)
 {
     for (int a = 0; a < m; a++) {
         w->rh[a] = -w->rF[a];
@@ -762,9 +766,20 @@ static int pcg(ws_t *w, int m, double delta, double cg_rtol)
     trsv_fwd(m, w->L, w->rh, &w->fl);
     memcpy(w->pp, w->rh, sizeof(double) * m);
     double rr = dot(m, w->rh, w->rh, &w->fl);
+    if (rr == 0.0) return CG_CONVERGED;
+    if (exact) {
+        w->cg_iters++;
+        w->fl += 1.0;                                  /* delta^2 */
+        if (rr >= delta * delta) {
+            double sig = trqsol_count(m, w->sh, w->pp, delta, &w->fl);
+            axpy(m, sig, w->pp, w->sh, &w->fl);
+            return CG_BOUNDARY;
+        }
+        memcpy(w->sh, w->pp, sizeof(double) * m);
+        return CG_CONVERGED;
+    }
     double tol = cg_rtol * sqrt(rr);
     w->fl += 2.0;
-    if (rr == 0.0) return CG_CONVERGED;
     for (int j = 0; j < m; j++) {
         w->cg_iters++;
         memcpy(w->z, w->pp, sizeof(double) * m);
@@ -848,10 +863,10 @@ static void subspace(ws_t *w, double delta, double cg_rtol)
             w->rF[a] = w->r[w->idx[a]];
             for (int b = 0; b < m; b++) w->A[a * m + b] = w->H[w->idx[a] * n + w->idx[b]];
         }
-        precond(w, m);
+        double shift = precond(w, m);
         w->lm = m;
         memcpy(w->lidx, w->idx, sizeof(int) * m);
-        int ex = pcg(w, m, delta, cg_rtol);
+        int ex = pcg(w, m, delta, cg_rtol, shift == 0.0);
         memcpy(w->wF, w->sh, sizeof(double) * m);
         trsv_bwd(m, w->L, w->wF, &w->fl);              /* w = L^-T s_hat */
         for (int i = 0; i < n; i++) w->w[i] = 0.0;
@@ -1070,7 +1085,7 @@ int32_t or_subspace_cg(int32_t m, const double *a, const double *r, double delta
     memcpy(w.A, a, sizeof(double) * mv * mv);
     memcpy(w.rF, r, sizeof(double) * mv);
     double shift = precond(&w, m);
-    int ex = pcg(&w, m, delta, cg_rtol);
+    int ex = pcg(&w, m, delta, cg_rtol, shift == 0.0);
     memcpy(shat, w.sh, sizeof(double) * mv);
     memcpy(wout, w.sh, sizeof(double) * mv);
     double fl = 0.0;

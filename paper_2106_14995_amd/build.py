@@ -12,21 +12,24 @@ CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIBDIR, "libtron_mi355x.so")
 OBJDIR = os.path.join(LIBDIR, "obj")
-SOURCES = ["tron_lib.hip", "admm.hip", "server.hip", "design.hip", "group.hip"]
+SOURCES = ["tron_lib.hip", "lane_br6.hip", "admm.hip", "server.hip", "design.hip", "group.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-# The solver kernels run one wave per SIMD (their register or LDS footprint allows no more),
-# so instruction-level parallelism, not occupancy, hides latency: schedule for ILP.
 # Packed FP32 instructions are switched off for the device code (the host pass of hipcc
-# reports that it does not know the feature; the device pass applies it).
+# reports that it does not know the feature; the device pass applies it: a float2
+# multiply-add compiles to v_pk_fma_f32 without the flag and to v_fma_f32 with it).
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
-         "-mllvm", "-amdgpu-sched-strategy=gcn-max-ilp",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+# Most solver kernels run one wave per SIMD (their register or LDS footprint allows no
+# more), so instruction-level parallelism, not occupancy, hides latency: schedule for ILP.
+# The branch-subproblem lane kernel is measured faster with the default scheduler.
+ILP = ["-mllvm", "-amdgpu-sched-strategy=gcn-max-ilp"]
+SOURCE_FLAGS = {"lane_br6.hip": []}
 
 
 def _compile(src, extra):
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, *(extra or []), "-c", "-o", obj, os.path.join(CSRC, src)]
+    cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, ILP), *(extra or []), "-c", "-o", obj, os.path.join(CSRC, src)]
     out = subprocess.run(cmd, capture_output=True, text=True)
     if out.returncode != 0:
         raise RuntimeError("HIP build failed:\n" + " ".join(cmd) + "\n" + out.stderr[-20000:])

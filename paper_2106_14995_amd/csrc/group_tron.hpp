@@ -208,7 +208,7 @@ struct GBR6 {
     static constexpr int N = 6;
     static constexpr int R = (N + G - 1) / G;
     static constexpr double pad = 0.0;
-    BR6T<false> b6;
+    BR6 b6;
     double hrow[R][N];
     double hdg[R];
 
@@ -493,7 +493,8 @@ struct GroupTron {
         }
         return -1.0;
     }
-    MT_INLINE int pcg(uint32_t fm, int m, const double (&rv)[R], double (&sh)[R], double cg_rtol)
+    // exact: no shift was needed; the first CG step is the whole solve (see lane_tron.hpp)
+    MT_INLINE int pcg(uint32_t fm, int m, const double (&rv)[R], double (&sh)[R], double cg_rtol, bool exact)
     {
         double rh[R], p[R];
         MT_UNROLL for (int r = 0; r < R; r++) {
@@ -503,8 +504,17 @@ struct GroupTron {
         fwd(rh);
         MT_UNROLL for (int r = 0; r < R; r++) p[r] = rh[r];
         double rr = dot(rh, rh);
-        const double tol2 = cg_rtol * cg_rtol * rr;
         if (rr == 0.0) return kCgConv;
+        if (exact) {
+            if (rr >= delta * delta) {
+                const double sig = trqsol(sh, p);
+                MT_UNROLL for (int r = 0; r < R; r++) sh[r] = sig * p[r];
+                return kCgBnd;
+            }
+            MT_UNROLL for (int r = 0; r < R; r++) sh[r] = p[r];
+            return kCgConv;
+        }
+        const double tol2 = cg_rtol * cg_rtol * rr;
         for (int j = 0; j < m; j++) {
             double z[R], q[R];
             MT_UNROLL for (int r = 0; r < R; r++) z[r] = p[r];
@@ -550,9 +560,9 @@ struct GroupTron {
             hmul(s, rv);
             MT_UNROLL for (int r = 0; r < R; r++) rv[r] += g[r];
             lfm = fm;
-            precond(fm);
+            const double shift = precond(fm);
             double w[R];
-            const int ex = pcg(fm, m, rv, w, cg_rtol);
+            const int ex = pcg(fm, m, rv, w, cg_rtol, shift == 0.0);
             bwd(w);
             double beta = 1.0;
             bool acc = false;

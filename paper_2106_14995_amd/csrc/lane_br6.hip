@@ -1,0 +1,8 @@
+// lane_br6.hip -- the lane kernel of the branch subproblem (BR6, n = 6), in a translation
+// unit of its own so that it is built with the compiler's default instruction scheduler
+// (measured faster for this kernel than the ILP scheduler the other solvers use).
+#include <hip/hip_runtime.h>
+
+#include "lane_kernels.hpp"
+
+void mt_launch_br6(const LaneArgs &a, hipStream_t st) { launch_lane<mt::BR6, 6>(a, st); }

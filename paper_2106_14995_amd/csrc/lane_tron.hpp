@@ -31,16 +31,6 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#ifndef MT_LANE_CG_EXACT
-#define MT_LANE_CG_EXACT 0
-#endif
-#ifndef MT_LANE_QFORM
-#define MT_LANE_QFORM 0
-#endif
-#ifndef MT_LANE_FULLF
-#define MT_LANE_FULLF 0
-#endif
-
 namespace mt {
 
 #define MT_INLINE __device__ __forceinline__
@@ -104,7 +94,6 @@ template <int N>
 struct QP4 {
     static constexpr int T = N * (N + 1) / 2;
     static constexpr double pad = 0.0;
-    static constexpr int kLdsDoubles = 0;
     double q[T];
     double c[N];
     double hd[N];
@@ -147,7 +136,6 @@ template <int N>
 struct HS45M {
     static constexpr int T = N * (N + 1) / 2;
     static constexpr double pad = 1.0;
-    static constexpr int kLdsDoubles = 0;
     double h[T];
     MT_INLINE void load(const double *__restrict__, int) {}
     MT_INLINE double fg(const double (&x)[N], double (&g)[N])
@@ -173,60 +161,25 @@ struct HS45M {
     MT_INLINE double H(int i, int j) const { return h[tri(i, j)]; }
 };
 
-// The dynamic LDS of the lane kernels (used by families that keep their parameters there).
-MT_INLINE double *lane_lds()
-{
-    extern __shared__ double mt_lane_lds[];
-    return mt_lane_lds;
-}
-
 // BR6: the branch subproblem (eq. exp-branch) with the flows of eqs. pij..qji and two
 // flow copies z coupled to p_ij, p_ji. Derivatives are taken in (v_i, v_j, D = th_i - th_j)
-// and mapped to (th_i, th_j) with dD/dth_i = 1, dD/dth_j = -1.
-// kLds: the 36 parameters live in the workgroup's LDS (pairs of doubles per lane, lane-major
-// within each pair block) and are read at each evaluation, instead of occupying 72 registers
-// for the whole solve; the solver's state then fits the register file without copies to
-// the accumulation registers. The LDS offset passes through an empty asm statement at each
-// evaluation so that the loads stay there instead of being hoisted out of the solve loop.
-template <bool kLds>
-struct BR6T {
+// and mapped to (th_i, th_j) with dD/dth_i = 1, dD/dth_j = -1. The 36 parameters stay in
+// registers for the whole solve.
+struct BR6 {
     static constexpr int N = 6;
     static constexpr int T = 21;
     static constexpr double pad = 0.0;
-    static constexpr int kLdsDoubles = kLds ? 36 : 0;  // per lane
-    double prm_r[kLds ? 1 : 36];
-    int loff;              // kLds: LDS index of this lane's first parameter pair
+    double prm_r[36];
     double cth, sth;       // cos, sin of th_i - th_j at the last fg point
     double h[T];
 
     MT_INLINE void load(const double *__restrict__ p, int)
     {
-        if constexpr (kLds) {
-            double *L = lane_lds();
-            loff = 2 * (int)threadIdx.x;
-            const int stride = 2 * (int)blockDim.x;
-            MT_UNROLL for (int k = 0; k < 18; k++) {
-                L[loff + k * stride] = p[2 * k];
-                L[loff + k * stride + 1] = p[2 * k + 1];
-            }
-        } else {
-            MT_UNROLL for (int k = 0; k < 36; k++) prm_r[k] = p[k];
-        }
+        MT_UNROLL for (int k = 0; k < 36; k++) prm_r[k] = p[k];
     }
     MT_INLINE void params(double (&q)[36]) const
     {
-        if constexpr (kLds) {
-            int o = loff;
-            asm volatile("" : "+v"(o));
-            const double *L = lane_lds();
-            const int stride = 2 * (int)blockDim.x;
-            MT_UNROLL for (int k = 0; k < 18; k++) {
-                q[2 * k] = L[o + k * stride];
-                q[2 * k + 1] = L[o + k * stride + 1];
-            }
-        } else {
-            MT_UNROLL for (int k = 0; k < 36; k++) q[k] = prm_r[k];
-        }
+        MT_UNROLL for (int k = 0; k < 36; k++) q[k] = prm_r[k];
     }
     // flow k = a own^2 + V (al cos D + be sin D), own = v_i for k < 2 and v_j otherwise
     static MT_INLINE double fa(const double (&p)[36], int k) { return k == 0 ? p[2] : k == 1 ? p[3] : k == 2 ? p[6] : p[7]; }
@@ -353,11 +306,6 @@ struct BR6T {
     MT_INLINE double H(int i, int j) const { return h[tri(i, j)]; }
 };
 
-#ifndef MT_BR6_PARAMS_LDS
-#define MT_BR6_PARAMS_LDS 0
-#endif
-using BR6 = BR6T<MT_BR6_PARAMS_LDS != 0>;
-
 // BR8L: BR6 plus the line limits of both ends as equalities with slacks,
 //   h_lm = p_lm^2 + q_lm^2 + sigma_lm - smax^2,  lm in {ij, ji},
 // entering through the augmented-Lagrangian terms lambda_lm h_lm + rho_h/2 h_lm^2 (section 1
@@ -369,8 +317,7 @@ struct BR8L {
     static constexpr int N = 8;
     static constexpr int T = 36;
     static constexpr double pad = 0.0;
-    static constexpr int kLdsDoubles = 0;
-    BR6T<false> b6;        // the BR6 part; its Hessian block also receives the limit terms
+    BR6 b6;                // the BR6 part; its Hessian block also receives the limit terms
     double smax2, lam[2], rhoh;
     double hs[2][4];       // slack rows of the Hessian against (v_i, v_j, th_i, th_j)
 
@@ -577,13 +524,9 @@ struct LaneTron {
         }
         if (!(dot(st, st) <= delta * delta)) return false;  // ||s|| <= delta
         const double gts = dot(g, st);
-#if MT_LANE_QFORM
-        const double q = fma(0.5, qform(st), gts);
-#else
         double hs[N];
         hmul(st, hs);
         const double q = fma(0.5, dot(st, hs), gts);
-#endif
         return q <= kMu0 * gts;
     }
 
@@ -626,24 +569,9 @@ struct LaneTron {
         alphac = a;
     }
 
-    // v'Hv from the packed lower triangle: sum_i v_i (H_ii v_i + 2 sum_{j<i} H_ij v_j)
-    MT_INLINE double qform(const double (&v)[N]) const
-    {
-        double acc = 0.0;
-        MT_UNROLL for (int i = 0; i < N; i++) {
-            double u = 0.0;
-            MT_UNROLL for (int j = 0; j < i; j++) u = fma(fam.H(i, j), v[j], u);
-            acc = fma(v[i], fma(fam.H(i, i), v[i], 2.0 * u), acc);
-        }
-        return acc;
-    }
-
     // Cholesky of the masked, shifted matrix: rows/columns outside fm are the identity.
-    // kFull: every variable is free (fm has all N bits), so no entry is masked.
-    template <bool kFull = false>
     MT_INLINE bool chol(uint32_t fm, double alpha)
     {
-        if constexpr (kFull) fm = (1u << N) - 1u;
         bool ok = true;
         MT_UNROLL for (int j = 0; j < N; j++) {
             const bool fj = (fm >> j) & 1u;
@@ -663,10 +591,8 @@ struct LaneTron {
     }
 
     // Returns the shift that succeeded, or -1 when the diagonal fallback was used.
-    template <bool kFull = false>
     MT_INLINE double precond(uint32_t fm)
     {
-        if constexpr (kFull) fm = (1u << N) - 1u;
         double dmn = 0.0, dmx = 0.0;
         bool first = true;
         MT_UNROLL for (int i = 0; i < N; i++) {
@@ -681,7 +607,7 @@ struct LaneTron {
         double alpha = dmn > 0.0 ? 0.0 : beta - dmn;
         for (int t = 0; t < kShiftTries; t++) {
             chol_tries++;
-            if (chol<kFull>(fm, alpha)) return alpha;
+            if (chol(fm, alpha)) return alpha;
             alpha = 2.0 * alpha > beta ? 2.0 * alpha : beta;
         }
         MT_UNROLL for (int i = 0; i < N; i++) {
@@ -696,12 +622,11 @@ struct LaneTron {
 
     // Steihaug CG in the preconditioned variable; result in sh (zero outside fm).
     // exact: L L^T is the unshifted block itself, so the preconditioned matrix is the
-    // identity and the first CG step (length 1 along r_hat, or to the boundary) is the
-    // whole solve.
-    template <bool kFull = false>
+    // identity and its first CG step (section 3: one iteration when no shift is needed),
+    // s_hat = r_hat cut at the radius, is the whole solve; the products that would only
+    // reproduce p are not formed.
     MT_INLINE int pcg(uint32_t fm, int m, const double (&r)[N], double (&sh)[N], double cg_rtol, bool exact)
     {
-        if constexpr (kFull) fm = (1u << N) - 1u;
         double rh[N], p[N];
         MT_UNROLL for (int i = 0; i < N; i++) {
             rh[i] = ((fm >> i) & 1u) ? -r[i] : 0.0;
@@ -710,9 +635,7 @@ struct LaneTron {
         fwd(rh);
         MT_UNROLL for (int i = 0; i < N; i++) p[i] = rh[i];
         double rr = dot(rh, rh);
-        const double tol2 = cg_rtol * cg_rtol * rr;  // (cg_rtol ||r0||)^2
         if (rr == 0.0) return kCgConv;
-#if MT_LANE_CG_EXACT
         if (exact) {
             cg_iters++;
             if (rr >= delta * delta) {
@@ -723,9 +646,7 @@ struct LaneTron {
             MT_UNROLL for (int i = 0; i < N; i++) sh[i] = p[i];
             return kCgConv;
         }
-#else
-        (void)exact;
-#endif
+        const double tol2 = cg_rtol * cg_rtol * rr;  // (cg_rtol ||r0||)^2
         for (int j = 0; j < m; j++) {
             cg_iters++;
             double z[N], q[N];
@@ -783,17 +704,8 @@ struct LaneTron {
             MT_UNROLL for (int i = 0; i < N; i++) r[i] += g[i];
             lfm = fm;
             double w[N];
-            int ex;
-#if MT_LANE_FULLF
-            if (fm == (1u << N) - 1u) {
-                const double sh = precond<true>(fm);
-                ex = pcg<true>(fm, m, r, w, cg_rtol, sh == 0.0);
-            } else
-#endif
-            {
-                const double sh = precond(fm);
-                ex = pcg(fm, m, r, w, cg_rtol, sh == 0.0);
-            }
+            const double shift = precond(fm);
+            const int ex = pcg(fm, m, r, w, cg_rtol, shift == 0.0);
             bwd(w);  // w = L^-T s_hat (zero outside F)
             // projected search on the model
             double beta = 1.0;
@@ -806,14 +718,9 @@ struct LaneTron {
                     xt[i] = clampf(fma(beta, w[i], xs[i]), lo[i], hi[i]);
                     d[i] = xt[i] - xs[i];
                 }
-#if MT_LANE_QFORM
-                const double rd = dot(r, d);
-                const double dq = fma(0.5, qform(d), rd);
-#else
                 hmul(d, hd);
                 const double rd = dot(r, d);
                 const double dq = fma(0.5, dot(d, hd), rd);
-#endif
                 if (dq <= kMu0 * rd) { acc = true; break; }
                 beta *= 0.5;
             }
@@ -889,12 +796,8 @@ struct LaneTron {
             MT_UNROLL for (int i = 0; i < N; i++) s[i] = xs[i] - x[i];
             const double snorm = step_norm(s);
             const double gts = dot(g, s);
-#if MT_LANE_QFORM
-            const double pred = -fma(0.5, qform(s), gts);
-#else
             hmul(s, hs);
             const double pred = -fma(0.5, dot(s, hs), gts);
-#endif
             iters++;
             if (!(pred > 0.0)) { status = kStalled; break; }
             double gt[N];

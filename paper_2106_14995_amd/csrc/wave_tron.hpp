@@ -624,7 +624,8 @@ struct WaveTron {
         return true;
     }
 
-    MT_INLINE void precond(const uint64_t (&fm)[R])
+    // Returns the shift that succeeded, or -1 when the diagonal fallback was used.
+    MT_INLINE double precond(const uint64_t (&fm)[R])
     {
         double mn = __builtin_inf(), mx = 0.0;
         MT_UNROLL for (int r = 0; r < R; r++) {
@@ -638,7 +639,7 @@ struct WaveTron {
         const double beta = 1e-3 * (mx > 1.0 ? mx : 1.0);
         double alpha = mn > 0.0 ? 0.0 : beta - mn;
         for (int t = 0; t < kShiftTries; t++) {
-            if (chol(fm, alpha)) return;
+            if (chol(fm, alpha)) return alpha;
             alpha = 2.0 * alpha > beta ? 2.0 * alpha : beta;
         }
         for (int j = 0; j < n; j++) {
@@ -657,6 +658,7 @@ struct WaveTron {
             }
         }
         sync();
+        return -1.0;
     }
 
     // component j of b * dinv, taken from its owner lane (wave-uniform result)
@@ -809,8 +811,10 @@ struct WaveTron {
         MT_UNROLL for (int r = 0; r < R; r++) fm[r] = __ballot(valid(r) && lo[r] < v[r] && v[r] < hi[r]);
     }
 
+    // exact: no shift was needed, so the preconditioned matrix is the identity and the first
+    // CG step, s_hat = r_hat cut at the radius, is the whole solve (see lane_tron.hpp)
     MT_INLINE int pcg(const uint64_t (&fm)[R], int m, const double (&rv)[R], double (&sh)[R],
-                      double cg_rtol)
+                      double cg_rtol, bool exact)
     {
         double rh[R], p[R];
         MT_UNROLL for (int r = 0; r < R; r++) {
@@ -820,8 +824,17 @@ struct WaveTron {
         fwd(rh);
         MT_UNROLL for (int r = 0; r < R; r++) p[r] = rh[r];
         double rr = dot(rh, rh);
-        const double tol2 = cg_rtol * cg_rtol * rr;
         if (rr == 0.0) return kCgConv;
+        if (exact) {
+            if (rr >= delta * delta) {
+                const double sig = trqsol(sh, p);
+                MT_UNROLL for (int r = 0; r < R; r++) sh[r] = sig * p[r];
+                return kCgBnd;
+            }
+            MT_UNROLL for (int r = 0; r < R; r++) sh[r] = p[r];
+            return kCgConv;
+        }
+        const double tol2 = cg_rtol * cg_rtol * rr;
         for (int j = 0; j < m; j++) {
             double z[R], q[R];
             MT_UNROLL for (int r = 0; r < R; r++) z[r] = p[r];
@@ -869,11 +882,11 @@ struct WaveTron {
             MT_UNROLL for (int r = 0; r < R; r++) s[r] = xs[r] - x[r];
             hmul(s, rv);
             MT_UNROLL for (int r = 0; r < R; r++) rv[r] += g[r];
-            precond(fm);
+            const double shift = precond(fm);
             has_l = true;
             MT_UNROLL for (int r = 0; r < R; r++) lfm[r] = fm[r];
             double w[R];
-            const int ex = pcg(fm, m, rv, w, cg_rtol);
+            const int ex = pcg(fm, m, rv, w, cg_rtol, shift == 0.0);
             bwd(w);
             double beta = 1.0;
             bool acc = false;

@@ -227,16 +227,16 @@ def test_flops_hand_ledger_one_iteration(orc):
       Cauchy: breakpoint 2; trial alpha=1 (gpstep 3, nrm2 3, gemv 2, dots 4,
               q 3) 15; alpha*10 1; trial 10 fails the radius (gpstep, nrm2) 6   = 24
       pass: gemv 2, r+g 1, shift rule 2, Cholesky 2, CG (forward solve 1,
-              dot 2, tolerance 2; r = 0 ends it) 5, back-transform 1,
-              search (gpstep 3, gemv 2, dots 4, change 3) 12                    = 25
+              dot 2; r = 0 ends it) 3, back-transform 1,
+              search (gpstep 3, gemv 2, dots 4, change 3) 12                    = 23
       s 1, step norm m(m+1)+2n+1 = 5, model (gemv 2, dots 4, 2) 8, f(xs) 13,
       f - ft 1, g(xs) 5, ratio 1, radius (gamma 2, alpha* 2, rule 3) 7          = 41
-    total 114; 1 iteration, 1 Cholesky, 2 Cauchy trials, 1 search trial."""
+    total 112; 1 iteration, 1 Cholesky, 2 Cauchy trials, 1 search trial."""
     r = orc.solve(_One(1.0, -1.0, -10.0, 10.0, 0.0), nthreads=1)
     st = r["stats"][0]
     assert r["status"][0] == 0 and r["x"][0] == 1.0
     assert list(st[1:]) == [1, 0, 1, 2, 1, 1, 1]
-    assert st[0] == 114
+    assert st[0] == 112
 
 
 def test_flops_hand_ledger_boundary_and_interpolation(orc):
@@ -245,18 +245,18 @@ def test_flops_hand_ledger_boundary_and_interpolation(orc):
       iteration 1 (alpha_c = 1):
         Cauchy: breakpoint 2; trial 1 fails the radius 6; alpha/10 1; trial 0.1
                 accepted 15                                                     = 24
-        pass: gemv 2, r+g 1, shift 2, Cholesky 2; CG: forward 1, dot 2, tol 2,
-              then one iteration (back 1, gemv 2, forward 1, dot 2, a 1, axpy 2,
-              nrm2 3 -> 9 >= 2: trqsol 3 dots + 9 = 15, axpy 2) 29;
-              back-transform 1; search accepted at beta = 1: 12                 = 54
+        pass: gemv 2, r+g 1, shift 2, Cholesky 2; CG with no shift, one exact step
+              (forward 1, dot 2, delta^2 1; 81 >= 4 so the step is cut at the
+              boundary: trqsol 3 dots + 9 = 15, axpy 2) 21;
+              back-transform 1; search accepted at beta = 1: 12                 = 41
         s 1, step norm 5, model 8, f 13, f-ft 1, g 5, ratio 1, radius 7,
         H at the accepted point 3                                               = 44
       iteration 2 (alpha_c = 0.1, x = 3, delta = 8):
         Cauchy: breakpoint 2; trial 0.1 accepted 15; *10 1; trial 1 accepted 15;
                 *10 1; trial 10 fails the radius 6                              = 40
-        pass (r = 0): 2 + 1 + 2 + 2 + 5 + 1 + 12                                = 25
+        pass (r = 0): 2 + 1 + 2 + 2 + 3 + 1 + 12                                = 23
         s 1, step norm 5, model 8, f 13, f-ft 1, g 5, ratio 1, radius 7         = 41
-    total 249."""
+    total 234."""
     r = orc.solve(_One(1.0, -10.0, -100.0, 100.0, 0.0), delta0=2.0, nthreads=1)
     st = r["stats"][0]
     assert r["status"][0] == 0 and r["x"][0] == 10.0
@@ -264,7 +264,7 @@ def test_flops_hand_ledger_boundary_and_interpolation(orc):
     # accepted steps
     assert list(st[1:]) == [2, 1, 2, 5, 2, 2, 2]
     assert r["delta"][0] == 8.0
-    assert st[0] == 249
+    assert st[0] == 234
 
 
 def test_flops_first_evaluation_per_family(orc):
