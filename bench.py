@@ -410,6 +410,42 @@ def bench_groups(args):
                       "rows": rows}), flush=True)
 
 
+def bench_workspace(args):
+    """Where the solver keeps its matrices (section 4.5, Table 3, for the whole solve rather
+    than one factorisation): registers (the lane kernel, n <= 8, and the group kernel of 16
+    lanes, n <= 16), LDS (the wavefront kernel) and a global-memory workspace read through L2
+    (the wavefront kernel's form beyond n = 128, forced below it), on 10,000 quartic problems
+    per size."""
+    import torch
+    from paper_2106_14995_amd import tron
+    from paper_2106_14995_amd import workloads as W
+    stream = torch.cuda.current_stream()
+    B = 10000
+    rows = []
+    for n in (8, 16, 32, 64, 128):
+        bt = W.qp4_batch(B, n, config_id=140 + n)
+        dev = tron.to_device(bt)
+        forms = [("lds", tron.plan_spec(lane_max_n=0)), ("global", tron.plan_spec(lane_max_n=0, wave_global=1))]
+        if n <= 8:
+            forms.insert(0, ("registers_lane", tron.plan_spec()))
+        if n <= 16:
+            forms.insert(0, ("registers_group16", tron.plan_spec(lane_max_n=0, group16=16)))
+        row = {"n": n}
+        for name, spec in forms:
+            h = tron.Batch(W.QP4, n, batch=B, spec=spec)
+            lat, total = time_solves(lambda: h.solve(*dev, stream=stream), args.steps, args.warmup, stream)
+            _, _, st, _ = h.solve(*dev, stream=stream)
+            torch.cuda.synchronize()
+            row[name + "_ms"] = 1e3 * total / args.steps
+            row[name + "_converged"] = int((st == 0).sum().item())
+            h.close()
+        rows.append(row)
+        log(f"n={n}: " + ", ".join(f"{k} {v:.3f}" for k, v in row.items() if k.endswith("_ms")))
+    print(json.dumps({"config": f"whole-solve workspace comparison, {B} quartic problems per size, gtol 1e-6",
+                      "rows": rows, "paper_context": "Table 3 (V100): shared memory 9.536 ms, global "
+                      "memory slower, for its hs45 batch"}), flush=True)
+
+
 def bench_serve(args):
     """Serving: requests of B = round(exp(U[0, ln 4096])) quartic problems with n log-uniform
     in [4,128], drawn as slices of a seeded pool. The saturated instance rate is measured with
@@ -497,7 +533,7 @@ def main():
     ap.add_argument("--mode", default="br6", choices=["br6", "copy"],
                     help="copy: a plain device-to-device copy of known size, used to scale the "
                          "FETCH_SIZE / WRITE_SIZE counters")
-    ap.add_argument("--config", default="br6", choices=["br6", "qp4", "uneven", "admm", "serve", "hs45m", "al", "design", "large", "groups"],
+    ap.add_argument("--config", default="br6", choices=["br6", "qp4", "uneven", "admm", "serve", "hs45m", "al", "design", "large", "groups", "workspace"],
                     help="br6: the headline batch (default); qp4: 256 x n=8 quartic problems "
                          "(oracle CPU seconds and GPU time); uneven: 50,000 quartic problems with "
                          "n log-uniform in [4,64], bucketed graph vs one launch per size; admm: "
@@ -506,7 +542,8 @@ def main():
                          "hs45m: the paper's hs45 variant, 10,000 instances, n = 1..32; al: the "
                          "multiplier loop on branch subproblems with line limits; design: the "
                          "Cholesky / triangular-solve / workspace variants of section 4; groups: "
-                         "the group-width sweep (lanes per instance)")
+                         "the group-width sweep (lanes per instance); workspace: registers vs "
+                         "LDS vs global memory for the whole solve")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per load level")
     ap.add_argument("--plan", default="", help="uneven: time only this plan (bucketed_streams, "
                     "bucketed_graph, persistent_8_graph, persistent_12_graph), e.g. for profiling")
@@ -536,7 +573,7 @@ def main():
     if args.config != "br6":
         {"qp4": bench_qp4, "uneven": bench_uneven, "admm": bench_admm, "serve": bench_serve,
          "hs45m": bench_hs45m, "al": bench_al, "design": bench_design, "large": bench_large,
-         "groups": bench_groups}[args.config](args)
+         "groups": bench_groups, "workspace": bench_workspace}[args.config](args)
         return
     log(f"generating {args.batch} BR6 instances")
     bt = W.br6_batch(args.batch, config_id=1)
@@ -628,6 +665,9 @@ def main():
             roof = {"bound": "hbm", "achieved": bytes_ / kern_s / 1e9, "peak": PEAK_HBM / 1e9,
                     "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
+        # both bounds, since the branch batch sits at the ridge (~9.7 flop/B against 9.8)
+        roof["frac_fp64"] = flops / kern_s / PEAK_FP64_VECTOR
+        roof["frac_hbm"] = bytes_ / kern_s / PEAK_HBM
         traffic = measured_traffic("lane_kernel<mt::BR6, 6>")
         roof["traffic"] = traffic
         if traffic is not None:

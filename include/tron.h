@@ -135,10 +135,13 @@ typedef struct {
                              over the group, section 4.2's thread configuration)             */
     int32_t group16;      /* 0, 8 or 16: instances with lane_max_n < n <= 16 go to the group
                              kernel of that width instead of the wavefront kernel            */
+    int32_t wave_global;  /* 1: quartic-family wavefront buckets up to n = 128 keep the Hessian
+                             and its factor in a global-memory workspace (L2) instead of LDS,
+                             as beyond n = 128 (section 4.5's workspace comparison)          */
 } tron_plan_spec;
 
 /* lane_max_n 8, edges 16/24/32/40/48/56/64/80/96/112/128, 4 streams, lane_block 64,
- * pool_waves 0, lane_group 1, group16 0. */
+ * pool_waves 0, lane_group 1, group16 0, wave_global 0. */
 void tron_default_plan_spec(tron_plan_spec *spec);
 /* tron_batch_create with an explicit plan (spec NULL = default). INVALID for a bad spec,
  * UNSUPPORTED when some n exceeds the largest edge. */

@@ -283,6 +283,12 @@ static void launch_wave_global(const LaneArgs &a, hipStream_t st)
 static void launch_wave_fam(tron_family fam, const LaneArgs &a, int nmax, hipStream_t st)
 {
     using namespace mt;
+    if (a.ws && nmax <= kLdsMaxN && fam == TRON_FAMILY_QP4) {
+        // the workspace form below the LDS limit (the plan's wave_global)
+        if (nmax <= 64) launch_wave_global<WaveFamQP4<1>>(a, st);
+        else launch_wave_global<WaveFamQP4<2>>(a, st);
+        return;
+    }
     if (fam == TRON_FAMILY_HS45M) {
         if (nmax <= 64) launch_wave<WaveFamHS45M<1>>(a, nmax, st);
         else launch_wave<WaveFamHS45M<2>>(a, nmax, st);
@@ -543,6 +549,7 @@ static void default_spec(tron_plan_spec *p)
     p->pool_waves = 0;
     p->lane_group = 1;
     p->group16 = 0;
+    p->wave_global = 0;
 }
 
 static tron_err check_spec(const tron_plan_spec &p)
@@ -551,7 +558,7 @@ static tron_err check_spec(const tron_plan_spec &p)
         p.streams > 8 || (p.lane_block != 64 && p.lane_block != 256) ||
         (p.pool_waves != 0 && p.pool_waves != 8 && p.pool_waves != 12) ||
         (p.lane_group != 1 && p.lane_group != 2 && p.lane_group != 4 && p.lane_group != 8) ||
-        (p.group16 != 0 && p.group16 != 8 && p.group16 != 16))
+        (p.group16 != 0 && p.group16 != 8 && p.group16 != 16) || (p.wave_global != 0 && p.wave_global != 1))
         return mt_fail(TRON_ERR_INVALID, "invalid plan spec");
     for (int i = 0; i < p.nedges; i++)
         if (p.edges[i] < 1 || p.edges[i] > 128 || (i > 0 && p.edges[i] <= p.edges[i - 1]))
@@ -754,7 +761,7 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
             b.nmax = h->n_uniform;
             b.lanes = 64;
             b.lane = nullptr;
-            if (b.nmax > kLdsMaxN &&
+            if ((b.nmax > kLdsMaxN || (sp.wave_global && h->fam == TRON_FAMILY_QP4)) &&
                 hipMalloc(&b.d_ws, sizeof(double) * (size_t)mt_wave_matrix_doubles(b.nmax) * (size_t)b.count) != hipSuccess)
                 return mt_fail(TRON_ERR_NOMEM, "matrix workspace allocation failed");
         }
@@ -788,7 +795,7 @@ static tron_err build_plan(tron_batch *h, const std::vector<int32_t> &n, hipStre
         b.lanes = lanes;
         b.count = (int64_t)list.size();
         b.lane = fn;
-        if (lanes == 64 && nmax > kLdsMaxN &&
+        if (lanes == 64 && (nmax > kLdsMaxN || (sp.wave_global && h->fam == TRON_FAMILY_QP4)) &&
             hipMalloc(&b.d_ws, sizeof(double) * (size_t)mt_wave_matrix_doubles(nmax) * list.size()) != hipSuccess)
             return mt_fail(TRON_ERR_NOMEM, "matrix workspace allocation failed");
         HIP_TRY(hipMalloc(&b.d_index, sizeof(int32_t) * list.size()));
@@ -1195,7 +1202,7 @@ static std::string spec_str(const tron_plan_spec &p)
     std::ostringstream o;
     o << p.lane_max_n << " " << p.streams << " " << p.lane_block << " " << p.nedges;
     for (int i = 0; i < p.nedges; i++) o << " " << p.edges[i];
-    o << " " << p.pool_waves << " " << p.lane_group << " " << p.group16;
+    o << " " << p.pool_waves << " " << p.lane_group << " " << p.group16 << " " << p.wave_global;
     return o.str();
 }
 
@@ -1210,6 +1217,7 @@ static bool spec_parse(const std::string &t, tron_plan_spec *p)
     if (!(in >> q.pool_waves)) q.pool_waves = 0;
     if (!(in >> q.lane_group)) q.lane_group = 1;
     if (!(in >> q.group16)) q.group16 = 0;
+    if (!(in >> q.wave_global)) q.wave_global = 0;
     if (check_spec(q) != TRON_OK) return false;
     *p = q;
     return true;

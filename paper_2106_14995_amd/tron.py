@@ -42,12 +42,12 @@ class AlOptions(C.Structure):
 class PlanSpec(C.Structure):
     _fields_ = [("lane_max_n", C.c_int32), ("nedges", C.c_int32), ("edges", C.c_int32 * 16),
                 ("streams", C.c_int32), ("lane_block", C.c_int32), ("pool_waves", C.c_int32),
-                ("lane_group", C.c_int32), ("group16", C.c_int32)]
+                ("lane_group", C.c_int32), ("group16", C.c_int32), ("wave_global", C.c_int32)]
 
     def describe(self):
         return dict(lane_max_n=self.lane_max_n, edges=list(self.edges[:self.nedges]),
                     streams=self.streams, lane_block=self.lane_block, pool_waves=self.pool_waves,
-                    lane_group=self.lane_group, group16=self.group16)
+                    lane_group=self.lane_group, group16=self.group16, wave_global=self.wave_global)
 
 
 class ServerConfig(C.Structure):
@@ -491,13 +491,14 @@ DEFAULT_EDGES = (16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128)
 
 
 def plan_spec(lane_max_n=8, edges=DEFAULT_EDGES, streams=4, lane_block=64, pool_waves=0,
-              lane_group=1, group16=0) -> PlanSpec:
+              lane_group=1, group16=0, wave_global=0) -> PlanSpec:
     """A launch plan (the defaults are the library's default plan); pool_waves 8 or 12 selects
     the persistent launch; lane_group 2/4/8 puts each instance with n <= lane_max_n on that
-    many lanes; group16 8/16 puts lane_max_n < n <= 16 on groups of that width."""
+    many lanes; group16 8/16 puts lane_max_n < n <= 16 on groups of that width; wave_global 1
+    keeps the quartic family's wavefront matrices in global memory instead of LDS."""
     p = PlanSpec()
     p.lane_max_n, p.nedges, p.streams, p.lane_block = lane_max_n, len(edges), streams, lane_block
-    p.pool_waves, p.lane_group, p.group16 = pool_waves, lane_group, group16
+    p.pool_waves, p.lane_group, p.group16, p.wave_global = pool_waves, lane_group, group16, wave_global
     for i, e in enumerate(edges):
         p.edges[i] = int(e)
     return p

@@ -548,3 +548,17 @@ def test_group_kernel_edge_cases(tron):
         one, _ = _solve_spec(tron, big.subset(np.array([37])), spec)
         vo = big.voff()
         assert np.array_equal(one["x"], full["x"][vo[37]:vo[38]]) and one["f"][0] == full["f"][37]
+
+
+def test_wave_global_workspace_below_the_lds_limit(tron):
+    """The workspace comparison's third form (plan spec wave_global): wavefront instances up
+    to n = 128 with the Hessian and factor in a global-memory workspace instead of LDS, one
+    and two rows per lane, against the oracle; a uniform batch takes the same form."""
+    sizes = W.loguniform_sizes(400, 2, 128, config_id=78)
+    bt = W.qp4_batch(400, sizes, config_id=78)
+    g, plan = _solve_spec(tron, bt, tron.plan_spec(wave_global=1))
+    check_parity(bt, g, oracle_ref(bt), convex=True, label="wave_global mixed")
+    uni = W.qp4_batch(200, 40, config_id=79)
+    g, plan = _solve_spec(tron, uni, tron.plan_spec(wave_global=1))
+    assert plan[0]["lanes"] == 64
+    check_parity(uni, g, oracle_ref(uni), convex=True, label="wave_global n=40")
