@@ -290,6 +290,11 @@ tron_err tron_server_wait(tron_server *s, int64_t ticket, double timeout_s);
  * latency_s is the time from submission to completion. BUSY if not finished. */
 tron_err tron_server_result(tron_server *s, int64_t ticket, double *x, double *f, int32_t *status,
                             int32_t *iters, double *latency_s);
+/* Take a queued request off the queue before it is admitted: it completes without a solve
+ * (waiters wake; tron_server_result then returns BUSY with a cancellation message and
+ * releases the ticket). BUSY when the request is already on the device or finished,
+ * INVALID for an unknown ticket. */
+tron_err tron_server_cancel(tron_server *s, int64_t ticket);
 /* Free a session's resident state (BUSY while it has a request outstanding). */
 tron_err tron_server_close_session(tron_server *s, uint64_t session);
 /* out4: requests done, instances done, device bytes in use, LDS bytes in flight. */

@@ -108,6 +108,7 @@ struct Request {
     size_t lds = 0;
     int state = 0;  // 0 queued, 1 on the device, 2 done
     tron_err err = TRON_OK;  // done without a solve: why (the result call reports it)
+    bool cancelled = false;  // taken off the queue by tron_server_cancel
     // session placement, copied at admission (the scheduler never reads the session map
     // outside the lock)
     size_t sess_off = 0;
@@ -671,7 +672,9 @@ extern "C" tron_err tron_server_result(tron_server *s, int64_t ticket, double *x
     if (r->state != 2) return mt_fail(TRON_ERR_BUSY, "request not finished");
     if (r->err != TRON_OK) {
         const tron_err e = r->err;
+        const bool cancelled = r->cancelled;
         s->tickets.erase(it);
+        if (cancelled) return mt_fail(e, "request was cancelled before it reached the device");
         return mt_fail(e, "request could not be admitted: resident sessions leave too little device memory");
     }
     if (x) std::copy(r->x.begin(), r->x.end(), x);
@@ -680,6 +683,32 @@ extern "C" tron_err tron_server_result(tron_server *s, int64_t ticket, double *x
     if (iters) std::copy(r->iters.begin(), r->iters.end(), iters);
     if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
     s->tickets.erase(it);
+    return TRON_OK;
+}
+
+extern "C" tron_err tron_server_cancel(tron_server *s, int64_t ticket)
+{
+    if (!s) return mt_fail(TRON_ERR_INVALID, "bad argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return mt_fail(TRON_ERR_INVALID, "unknown ticket");
+    Request *r = it->second.get();
+    if (r->state != 0) return mt_fail(TRON_ERR_BUSY, r->state == 1 ? "request is on the device" : "request is finished");
+    auto q = std::find(s->queue.begin(), s->queue.end(), r);
+    if (q == s->queue.end()) return mt_fail(TRON_ERR_BUSY, "request is being admitted");
+    s->queue.erase(q);
+    // completed without a solve: waiters wake, the result call reports the cancellation
+    // and releases the ticket
+    r->cancelled = true;
+    r->err = TRON_ERR_BUSY;
+    r->state = 2;
+    r->t_done = clock_t_::now();
+    if (r->session) {
+        auto si = s->sessions.find(r->session);
+        if (si != s->sessions.end()) si->second.outstanding--;
+    }
+    s->done_cv.notify_all();
+    s->cv.notify_one();
     return TRON_OK;
 }
 

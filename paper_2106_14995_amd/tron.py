@@ -71,6 +71,7 @@ EXPORTS = ("tron_default_options", "tron_last_error", "tron_param_size", "tron_b
            "admm_state_size", "admm_create", "admm_step", "admm_get_state", "admm_set_state",
            "admm_destroy", "tron_server_default_config", "tron_server_create", "tron_server_submit",
            "tron_server_poll", "tron_server_wait", "tron_server_result", "tron_server_close_session",
+           "tron_server_cancel",
            "tron_server_stats", "tron_server_destroy", "tron_batch_set_timestamps", "tron_clock_rate_hz",
            "tron_default_plan_spec", "tron_batch_create_ex", "tron_autotune",
            "tron_default_al_options", "tron_al_solve", "tron_design_chol", "tron_design_trsv",
@@ -142,6 +143,7 @@ def lib():
         L.tron_server_wait.argtypes = [P, I64, C.c_double]
         L.tron_server_result.argtypes = [P, I64, P, P, P, P, C.POINTER(C.c_double)]
         L.tron_server_close_session.argtypes = [P, C.c_uint64]
+        L.tron_server_cancel.argtypes = [P, I64]
         L.tron_server_stats.argtypes = [P, P]
         L.tron_server_destroy.argtypes = [P]
         if hasattr(L, "admm_state_size"):
@@ -456,13 +458,24 @@ class Server:
         _check(lib().tron_server_wait(self._h, ticket, float(timeout)))
 
     def result(self, ticket):
-        B, nsum = self._sizes.pop(ticket)
+        B, nsum = self._sizes.get(ticket, (0, 0))
         x = np.empty(nsum); f = np.empty(B)
         st = np.empty(B, dtype=np.int32); it = np.empty(B, dtype=np.int32)
         lat = C.c_double()
         p = lambda a: a.ctypes.data_as(C.c_void_p)
-        _check(lib().tron_server_result(self._h, ticket, p(x), p(f), p(st), p(it), C.byref(lat)))
+        try:
+            _check(lib().tron_server_result(self._h, ticket, p(x), p(f), p(st), p(it), C.byref(lat)))
+        except TronError as e:
+            if "not finished" not in str(e):  # the library released the ticket
+                self._sizes.pop(ticket, None)
+            raise
+        self._sizes.pop(ticket, None)
         return dict(x=x, f=f, status=st, iters=it, latency=lat.value)
+
+    def cancel(self, ticket):
+        """Take a queued request off the queue (TronError BUSY if it already reached the
+        device); its result call then raises with the cancellation."""
+        _check(lib().tron_server_cancel(self._h, ticket))
 
     def close_session(self, session):
         _check(lib().tron_server_close_session(self._h, C.c_uint64(session)))

@@ -166,3 +166,40 @@ def test_resident_sessions_limit_admission(T):
     srv.wait(t2)
     assert np.all(srv.result(t2)["status"] == 0)
     srv.close()
+
+
+def test_cancel_queued_requests(T):
+    """A queued request can be taken off the queue. One group on the device at a time, and
+    ahead of the request three requests of 1,000 hs45-variant instances at n = 128 from
+    random starts (one instance per CU at a time: tens of milliseconds on the device, a few
+    megabytes to submit), so the last submission is still queued when it is cancelled. Its
+    result call reports the cancellation (BUSY) and releases the ticket, its session can take
+    a new request, and every other request completes at the known minimiser (the upper
+    corner). A request already finished cannot be cancelled."""
+    srv = T.Server(W.HS45M, max_inflight=1, streams=1, coalesce=False)
+    heads = [W.hs45m_random_start(1000, 128, config_id=140 + i) for i in range(3)]
+    last = W.hs45m_random_start(50, 16, config_id=150)
+    tickets = [srv.submit_batch(b) for b in heads]
+    t_last = srv.submit_batch(last, session=7)
+    srv.cancel(t_last)
+    srv.wait(t_last)
+    with pytest.raises(T.TronError) as e:
+        srv.result(t_last)
+    assert e.value.code == 5 and "cancelled" in str(e.value)
+    with pytest.raises(T.TronError):
+        srv.result(t_last)  # the ticket is released
+    for t, b in zip(tickets, heads):
+        srv.wait(t)
+        r = srv.result(t)
+        assert np.all(r["status"] == 0) and np.array_equal(r["x"], b.hi)
+    t2 = srv.submit_batch(last, session=7)  # the session is free again
+    srv.wait(t2)
+    r2 = srv.result(t2)
+    assert np.all(r2["status"] == 0) and np.array_equal(r2["x"], last.hi)
+    t3 = srv.submit_batch(last)
+    srv.wait(t3)
+    with pytest.raises(T.TronError) as e:
+        srv.cancel(t3)
+    assert e.value.code == 5
+    srv.result(t3)
+    srv.close()
