@@ -113,6 +113,7 @@ def lib():
         L = C.CDLL(_build.LIB)
         P, I32, I64 = C.c_void_p, C.c_int32, C.c_int64
         L.tron_last_error.restype = C.c_char_p
+        L.tron_last_error.argtypes = []
         L.tron_default_options.argtypes = [C.POINTER(Options)]
         L.tron_param_size.restype = I64
         L.tron_param_size.argtypes = [I32, I32]
@@ -133,8 +134,10 @@ def lib():
         L.tron_design_chol.argtypes = [I32, I64, I32, P, P, P, P]
         L.tron_design_trsv.argtypes = [I32, I64, I32, P, P, P, I32, P]
         L.tron_clock_rate_hz.restype = I64
+        L.tron_clock_rate_hz.argtypes = []
         L.tron_solve_noalloc.argtypes = [I32, I64, I32, C.POINTER(Options)] + [P] * 9
         L.tron_noalloc_scratch_bytes.restype = I64
+        L.tron_noalloc_scratch_bytes.argtypes = []
         L.tron_batch_set_timestamps.argtypes = [P, P]
         L.tron_server_default_config.argtypes = [C.POINTER(ServerConfig)]
         L.tron_server_create.argtypes = [C.POINTER(P), I32, C.POINTER(ServerConfig)]

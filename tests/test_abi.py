@@ -91,3 +91,27 @@ def test_create_rejects_bad_arguments_before_touching_the_device():
     assert L.tron_batch_create(C.byref(h), tron.BR6, 1, None, 5, None, None) == 1
     assert L.tron_batch_create(C.byref(h), tron.QP4, -1, None, 4, None, None) == 1
     assert b"invalid" in L.tron_last_error() or len(L.tron_last_error()) > 0
+
+
+def declared_arities():
+    src = "".join(open(os.path.join(ROOT, "include", h)).read() for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+                  if h.endswith(".h"))
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    out = {}
+    for name, params in re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([a-z_][a-z0-9_]*)\s*\(([^;{]*?)\)\s*;",
+                                   src, flags=re.M | re.S):
+        params = params.strip()
+        out[name] = 0 if params in ("", "void") else params.count(",") + 1
+    return out
+
+
+def test_binding_declares_every_call_with_the_header_arity():
+    """Every declared call has ctypes argument types in the binding, as many as the header
+    declares: an undeclared call would pass 64-bit pointers and sizes as C ints."""
+    from paper_2106_14995_amd import tron
+    L = tron.lib()
+    ar = declared_arities()
+    assert set(ar) == set(declared_functions())
+    bad = {n: (k, getattr(L, n).argtypes) for n, k in ar.items()
+           if getattr(L, n).argtypes is None or len(getattr(L, n).argtypes) != k}
+    assert not bad, bad
