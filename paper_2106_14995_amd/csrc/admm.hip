@@ -413,6 +413,7 @@ extern "C" tron_err admm_create(admm **out, const admm_network *n, const tron_op
         (n->ngen > 0 && (!n->gen_bus || !n->gen_cost || !n->gen_lim)))
         return mt_fail(TRON_ERR_INVALID, "null network array");
     if (!(n->rho > 0.0)) return mt_fail(TRON_ERR_INVALID, "rho must be positive");
+    mt_prepare_br6();
     const int G = n->ngen, L = n->nbranch, B = n->nbus;
     // adjacency in increasing index order
     std::vector<int32_t> gptr(B + 1, 0), eptr(B + 1, 0);

@@ -208,7 +208,7 @@ struct GBR6 {
     static constexpr int N = 6;
     static constexpr int R = (N + G - 1) / G;
     static constexpr double pad = 0.0;
-    BR6 b6;
+    BR6R b6;
     double hrow[R][N];
     double hdg[R];
 

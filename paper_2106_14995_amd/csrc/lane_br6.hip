@@ -6,3 +6,10 @@
 #include "lane_kernels.hpp"
 
 void mt_launch_br6(const LaneArgs &a, hipStream_t st) { launch_lane<mt::BR6, 6>(a, st); }
+
+// the parameters of a 256-lane workgroup take 72 KB of LDS, above the default limit
+void mt_prepare_br6()
+{
+    (void)hipFuncSetAttribute((const void *)lane_kernel<mt::BR6, 6>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)(sizeof(double) * mt::BR6::kLdsDoubles * kLaneBlock));
+}

@@ -55,5 +55,6 @@ static void launch_lane(const LaneArgs &a, hipStream_t st)
 {
     const int blk = a.lane_block == 64 ? 64 : kLaneBlock;
     const unsigned grid = (unsigned)((a.count + blk - 1) / blk);
-    if (grid) hipLaunchKernelGGL((lane_kernel<F, N>), dim3(grid), dim3(blk), 0, st, a);
+    const size_t lds = sizeof(double) * (size_t)F::kLdsDoubles * (size_t)blk;
+    if (grid) hipLaunchKernelGGL((lane_kernel<F, N>), dim3(grid), dim3(blk), lds, st, a);
 }

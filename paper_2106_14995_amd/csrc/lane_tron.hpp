@@ -94,6 +94,7 @@ template <int N>
 struct QP4 {
     static constexpr int T = N * (N + 1) / 2;
     static constexpr double pad = 0.0;
+    static constexpr int kLdsDoubles = 0;  // per lane, in the lane kernel's dynamic LDS
     double q[T];
     double c[N];
     double hd[N];
@@ -136,6 +137,7 @@ template <int N>
 struct HS45M {
     static constexpr int T = N * (N + 1) / 2;
     static constexpr double pad = 1.0;
+    static constexpr int kLdsDoubles = 0;
     double h[T];
     MT_INLINE void load(const double *__restrict__, int) {}
     MT_INLINE double fg(const double (&x)[N], double (&g)[N])
@@ -161,25 +163,55 @@ struct HS45M {
     MT_INLINE double H(int i, int j) const { return h[tri(i, j)]; }
 };
 
+// The lane kernel's dynamic LDS (families with kLdsDoubles > 0 keep data there).
+MT_INLINE double *lane_lds()
+{
+    extern __shared__ double mt_lane_lds[];
+    return mt_lane_lds;
+}
+
 // BR6: the branch subproblem (eq. exp-branch) with the flows of eqs. pij..qji and two
 // flow copies z coupled to p_ij, p_ji. Derivatives are taken in (v_i, v_j, D = th_i - th_j)
-// and mapped to (th_i, th_j) with dD/dth_i = 1, dD/dth_j = -1. The 36 parameters stay in
-// registers for the whole solve.
-struct BR6 {
+// and mapped to (th_i, th_j) with dD/dth_i = 1, dD/dth_j = -1.
+// kLds: the 36 parameters live in the workgroup's LDS and are read at each evaluation; the
+// lane's registers then hold only the solver state. Each wave has a block of 36 x 64 doubles,
+// parameter k of lane l at k 64 + l, so that the 36 reads share one address register and
+// differ by immediate offsets. The index passes through an empty asm statement at each
+// evaluation, so that the loads stay there instead of being hoisted out of the solve loop
+// into registers. Otherwise the parameters stay in registers for the whole solve (the form
+// the group kernel and BR8L use).
+template <bool kLds>
+struct BR6T {
     static constexpr int N = 6;
     static constexpr int T = 21;
     static constexpr double pad = 0.0;
-    double prm_r[36];
+    static constexpr int kLdsDoubles = kLds ? 36 : 0;
+    double prm_r[kLds ? 1 : 36];
     double cth, sth;       // cos, sin of th_i - th_j at the last fg point
     double h[T];
 
+    // the lane's first parameter in the workgroup's LDS (its wave's block, then the lane)
+    static MT_INLINE int lds_base() { return ((int)threadIdx.x >> 6) * (36 * 64) + ((int)threadIdx.x & 63); }
+
     MT_INLINE void load(const double *__restrict__ p, int)
     {
-        MT_UNROLL for (int k = 0; k < 36; k++) prm_r[k] = p[k];
+        if constexpr (kLds) {
+            double *L = lane_lds() + lds_base();
+            MT_UNROLL for (int k = 0; k < 36; k++) L[64 * k] = p[k];
+        } else {
+            MT_UNROLL for (int k = 0; k < 36; k++) prm_r[k] = p[k];
+        }
     }
     MT_INLINE void params(double (&q)[36]) const
     {
-        MT_UNROLL for (int k = 0; k < 36; k++) q[k] = prm_r[k];
+        if constexpr (kLds) {
+            int o = lds_base();
+            asm volatile("" : "+v"(o));
+            const double *L = lane_lds() + o;
+            MT_UNROLL for (int k = 0; k < 36; k++) q[k] = L[64 * k];
+        } else {
+            MT_UNROLL for (int k = 0; k < 36; k++) q[k] = prm_r[k];
+        }
     }
     // flow k = a own^2 + V (al cos D + be sin D), own = v_i for k < 2 and v_j otherwise
     static MT_INLINE double fa(const double (&p)[36], int k) { return k == 0 ? p[2] : k == 1 ? p[3] : k == 2 ? p[6] : p[7]; }
@@ -306,6 +338,10 @@ struct BR6 {
     MT_INLINE double H(int i, int j) const { return h[tri(i, j)]; }
 };
 
+// the lane kernel's form (parameters in LDS) and the register form
+struct BR6 : BR6T<true> {};
+using BR6R = BR6T<false>;
+
 // BR8L: BR6 plus the line limits of both ends as equalities with slacks,
 //   h_lm = p_lm^2 + q_lm^2 + sigma_lm - smax^2,  lm in {ij, ji},
 // entering through the augmented-Lagrangian terms lambda_lm h_lm + rho_h/2 h_lm^2 (section 1
@@ -317,7 +353,8 @@ struct BR8L {
     static constexpr int N = 8;
     static constexpr int T = 36;
     static constexpr double pad = 0.0;
-    BR6 b6;                // the BR6 part; its Hessian block also receives the limit terms
+    static constexpr int kLdsDoubles = 0;
+    BR6R b6;               // the BR6 part; its Hessian block also receives the limit terms
     double smax2, lam[2], rhoh;
     double hs[2][4];       // slack rows of the Hessian against (v_i, v_j, th_i, th_j)
 

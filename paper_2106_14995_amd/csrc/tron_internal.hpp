@@ -36,6 +36,8 @@ typedef void (*lane_launch_fn)(const LaneArgs &, hipStream_t);
 
 // Launch the BR6 lane kernel (n = 6) over a.count instances.
 void mt_launch_br6(const LaneArgs &a, hipStream_t st);
+// Let the BR6 lane kernel take the LDS of its largest workgroup (once per process and device).
+void mt_prepare_br6();
 // The lane kernel for (family, N <= 8), or null when unsupported.
 lane_launch_fn mt_lane_launcher(tron_family fam, int N);
 // The wavefront-per-instance kernel of the family (QP4 or HS45M) for instances with
@@ -44,7 +46,8 @@ lane_launch_fn mt_lane_launcher(tron_family fam, int N);
 void mt_launch_wave(tron_family fam, const LaneArgs &a, int nmax, hipStream_t st);
 // LDS bytes the wave kernel uses for one instance of size n (its bucket's footprint).
 size_t mt_wave_lds_bytes(int nmax);
-// Make the wave kernels accept the largest LDS request (once per process and device).
+// Make the wave kernels and the BR6 lane kernel accept their largest LDS request (once per
+// process and device).
 void mt_prepare_wave_kernels();
 
 // Record an error message for tron_last_error() and return `code`.

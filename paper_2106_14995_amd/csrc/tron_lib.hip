@@ -519,6 +519,7 @@ void mt_prepare_wave_kernels()
     const void *k128[] = {(const void *)wave_kernel_big<WaveFamQP4<2>>, (const void *)wave_kernel_big<WaveFamHS45M<2>>};
     for (const void *k : k64) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, small);
     for (const void *k : k128) (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+    mt_prepare_br6();
 }
 
 static void launch_bucket(tron_family fam, const Bucket &b, const LaneArgs &a0, hipStream_t st)

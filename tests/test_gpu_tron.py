@@ -71,6 +71,19 @@ def test_br6_full_size(tron):
     check_parity(bt, g, oracle_ref(bt), convex=False, label="br6 65536")
 
 
+def test_br6_workgroup_sizes_agree(tron):
+    """The branch lane kernel keeps each wave's parameters in its own block of the workgroup's
+    LDS: 64- and 256-lane workgroups (18 and 72 KB) give the same bits, with a ragged last
+    workgroup, and match the oracle."""
+    bt = W.br6_batch(3 * 256 + 61, config_id=5)
+    g64, plan = _solve_spec(tron, bt, tron.plan_spec(lane_block=64))
+    g256, _ = _solve_spec(tron, bt, tron.plan_spec(lane_block=256))
+    assert plan[0]["lanes"] == 1
+    for k in ("x", "f", "status", "iters"):
+        assert np.array_equal(g64[k], g256[k]), k
+    check_parity(bt, g256, oracle_ref(bt), convex=False, label="br6 256-lane workgroups")
+
+
 def _uneven_setup(tron, B=50000):
     import torch
     sizes = W.loguniform_sizes(B, 4, 64, config_id=3)
