@@ -221,7 +221,7 @@ template <class Fam>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) void wave_kernel(LaneArgs a) { wave_body<Fam, false>(a); }
 
 // n_max <= kWaveTinyN: the LDS request (8.4 KB at 32) allows four or more instances per SIMD,
-// so this build is held to four waves' worth of registers
+// so this variant is held to four waves' worth of registers
 constexpr int kWaveTinyN = 32;
 template <class Fam>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void wave_kernel_tiny(LaneArgs a)
