@@ -199,6 +199,15 @@ def bench_uneven(args):
                            "plan": best_key, "flops_per_batch": flops,
                            "note": "wave instances with n > 16 use FP64 matrix-core products in their "
                                    "factorisation; the peak is the FP64 vector one"}
+        # HBM bytes of the persistent launch's wavefront kernel, from its committed counters
+        if best_key == "persistent_12_graph":
+            kname = "pool_kernel<mt::WaveFamQP4<1>, mt::WaveFamQP4<1>, 12>"
+            tr = measured_traffic(kname)
+            if tr is not None:
+                rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kname]
+                res["roofline"].update({"traffic": tr, "traffic_kernel": kname,
+                                        "traffic_unit": "bytes per launch (FETCH_SIZE x2.000 + WRITE_SIZE x1.000)",
+                                        "traffic_over_algorithmic": tr / rec["algorithmic_bytes_per_launch"]})
         res["cpu_baseline"] = {"value": cb["value"], "unit": "solves/s", "cores": cb["threads"], "kind": "oracle",
                                "sample": f"the same {B}-instance batch, {cb['reps']} passes, {cb['wall']:.2f} s wall"}
     print(json.dumps(res), flush=True)
