@@ -1,6 +1,6 @@
 // lane_br6.hip -- the lane kernel of the branch subproblem (BR6, n = 6), in a translation
-// unit of its own so that it is built with the compiler's default instruction scheduler
-// (measured faster for this kernel than the ILP scheduler the other solvers use).
+// unit of its own (it compiles beside the other sources), with the LDS set-up its
+// parameter blocks need.
 #include <hip/hip_runtime.h>
 
 #include "lane_kernels.hpp"
