@@ -49,6 +49,40 @@ def measured_traffic(kernel):
     return rec["hbm_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
 
 
+def measured_peaks(stream):
+    """Achievable rates on this device, the measured references beside the published peaks:
+    FP64 from the library's FMA-chain kernel (8 waves per SIMD, 8 independent chains per lane),
+    HBM from a 512 MiB device-to-device copy (bytes read plus bytes written). Each is the best
+    of five timed launches after one warm-up."""
+    import torch
+    from paper_2106_14995_amd import tron
+    blocks, iters = 256 * 8, 20000
+    sink = torch.empty(blocks * 256, dtype=torch.float64, device="cuda")
+    flops = blocks * 256 * 8 * iters * 2.0
+    src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    nbytes = 2.0 * src.numel() * 8
+
+    def best(fn, work):
+        fn()
+        torch.cuda.synchronize()
+        rates = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rates.append(work / (e0.elapsed_time(e1) * 1e-3))
+        return max(rates)
+
+    fp64 = best(lambda: tron.design_fma_peak(blocks, iters, sink, stream=stream), flops)
+    hbm = best(lambda: dst.copy_(src), nbytes)
+    return {"fp64_tflops": fp64 / 1e12, "hbm_gbs": hbm / 1e9,
+            "fp64_kernel": f"FMA chains, {blocks} x 256 lanes x 8 chains x {iters}",
+            "hbm_kernel": "device-to-device copy of 512 MiB"}
+
+
 def cpu_baseline(bt, budget_s):
     """The oracle (as it stands) on all host cores over the same batch, repeated until about
     `budget_s` seconds of CPU work; also returns its algorithmic flop count per instance."""
@@ -685,6 +719,11 @@ def main():
         roof["flops_per_instance"] = cb["flops_per_instance"]
         roof["bytes_per_instance"] = BR6_BYTES
         roof["hbm_gbs_algorithmic"] = bytes_ / kern_s / 1e9
+        log("measured peaks (FMA chains, copy)")
+        mp = measured_peaks(stream)
+        roof["measured_peaks"] = mp
+        roof["frac_of_measured"] = {"fp64": flops / kern_s / (mp["fp64_tflops"] * 1e12),
+                                    "hbm": bytes_ / kern_s / (mp["hbm_gbs"] * 1e9)}
         result["roofline"] = roof
         result["cpu_baseline"] = {
             "value": cb["value"], "unit": "solves/s", "cores": cb["threads"], "kind": "oracle",

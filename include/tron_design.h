@@ -60,6 +60,16 @@ enum {
 tron_err tron_design_trsv(int32_t variant, int64_t count, int32_t n, const double *d_l,
                           const double *d_b, double *d_x, int32_t reps, void *stream);
 
+/* Achievable FP64 vector rate on this device, the measured reference for the roofline (not a
+ * step of the method). `blocks` workgroups of 256 lanes; each lane runs 8 independent chains
+ * of `iters` fused multiply-adds x <- x a + b with a = 1 - 2^-20 and b = 2^-20, whose fixed
+ * point is 1, from x0 = 1 + (c + (lane mod 8) + 1) 2^-10 for chain c, so every value stays
+ * in [1, 2]; the lane's sum of its 8 chains goes to d_sink[global lane index] (blocks x 256
+ * doubles, caller-owned device memory) so that no chain is dropped. FP64 flops issued =
+ * blocks x 256 x 8 x iters x 2; the caller times the launch. Asynchronous on `stream`.
+ * TRON_ERR_INVALID for a null sink, blocks < 1 or iters < 1. */
+tron_err tron_design_fma_peak(int64_t blocks, int32_t iters, double *d_sink, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -214,7 +214,32 @@ __global__ __launch_bounds__(64) void trsv_kernel(int variant, int64_t count, in
     if (i < n) x[p * n + i] = out;
 }
 
+// Eight independent FMA chains per lane: enough independent work per wave to cover the
+// FP64 pipeline's latency, so that the launch measures issue rate, not dependency stalls.
+__global__ __launch_bounds__(256) void fma_peak_kernel(int32_t iters, double a, double b, double *sink)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    double x[8];
+    MT_UNROLL for (int c = 0; c < 8; c++) x[c] = 1.0 + (double)(c + (int)(t & 7) + 1) * 0x1p-10;
+    for (int k = 0; k < iters; k++) {
+        MT_UNROLL for (int c = 0; c < 8; c++) x[c] = fma(x[c], a, b);
+    }
+    double s = 0.0;
+    MT_UNROLL for (int c = 0; c < 8; c++) s += x[c];
+    sink[t] = s;
+}
+
 }  // namespace
+
+extern "C" tron_err tron_design_fma_peak(int64_t blocks, int32_t iters, double *d_sink, void *stream)
+{
+    if (!d_sink || blocks < 1 || blocks > INT32_MAX || iters < 1)
+        return mt_fail(TRON_ERR_INVALID, "invalid FMA-rate benchmark arguments");
+    hipLaunchKernelGGL(fma_peak_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, (int)iters,
+                       1.0 - 0x1p-20, 0x1p-20, d_sink);
+    HIP_TRY(hipGetLastError());
+    return TRON_OK;
+}
 
 extern "C" tron_err tron_design_chol(int32_t variant, int64_t count, int32_t n, const double *d_a,
                                      double *d_l, int32_t *d_info, void *stream)

@@ -75,6 +75,7 @@ EXPORTS = ("tron_default_options", "tron_last_error", "tron_param_size", "tron_b
            "tron_server_stats", "tron_server_destroy", "tron_batch_set_timestamps", "tron_clock_rate_hz",
            "tron_default_plan_spec", "tron_batch_create_ex", "tron_autotune",
            "tron_default_al_options", "tron_al_solve", "tron_design_chol", "tron_design_trsv",
+           "tron_design_fma_peak",
            "tron_solve_noalloc", "tron_noalloc_scratch_bytes")
 CHOL_LEFT_LDS, CHOL_RIGHT_LDS, CHOL_LEFT_GLOBAL, CHOL_BLOCKED_MFMA = 0, 1, 2, 3
 TRSV_IMPLICIT, TRSV_PADDED, TRSV_EXPLICIT, TRSV_GLOBAL = 0, 1, 2, 3
@@ -133,6 +134,7 @@ def lib():
         L.tron_al_solve.argtypes = [P, C.POINTER(AlOptions)] + [P] * 11
         L.tron_design_chol.argtypes = [I32, I64, I32, P, P, P, P]
         L.tron_design_trsv.argtypes = [I32, I64, I32, P, P, P, I32, P]
+        L.tron_design_fma_peak.argtypes = [I64, I32, P, P]
         L.tron_clock_rate_hz.restype = I64
         L.tron_clock_rate_hz.argtypes = []
         L.tron_solve_noalloc.argtypes = [I32, I64, I32, C.POINTER(Options)] + [P] * 9
@@ -356,6 +358,18 @@ def design_trsv(variant, l, b, x=None, reps=1, stream=None):
                                   _dev(b, torch.float64, count * n, "b"), _dev(x, torch.float64, count * n, "x"),
                                   reps, _stream_ptr(stream)))
     return x
+
+
+def design_fma_peak(blocks, iters, sink=None, stream=None):
+    """tron_design_fma_peak: one launch of the FP64 FMA-rate kernel (blocks x 256 lanes, 8 chains
+    of `iters` fused multiply-adds each); returns the per-lane sums. Flops issued:
+    blocks x 256 x 8 x iters x 2."""
+    import torch
+    if sink is None:
+        sink = torch.empty(int(blocks) * 256, dtype=torch.float64, device="cuda")
+    _check(lib().tron_design_fma_peak(int(blocks), int(iters), _dev(sink, torch.float64, int(blocks) * 256, "sink"),
+                                      _stream_ptr(stream)))
+    return sink
 
 
 def to_device(batch, device="cuda"):

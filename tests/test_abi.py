@@ -73,6 +73,9 @@ def test_design_calls_reject_bad_arguments_before_touching_the_device():
     assert L.tron_design_chol(0, 0, 4, None, None, None, None) == 0    # empty batch
     assert L.tron_design_trsv(0, 1, 4, None, None, None, 0, None) == 1  # reps < 1
     assert L.tron_design_trsv(4, 1, 4, None, None, None, 1, None) == 1  # unknown variant
+    assert L.tron_design_fma_peak(1, 1, None, None) == 1                # null sink
+    assert L.tron_design_fma_peak(0, 1, None, None) == 1                # no workgroup
+    assert L.tron_design_fma_peak(1, 0, None, None) == 1                # no iteration
 
 
 def test_al_solve_rejects_bad_arguments_before_touching_the_device():

@@ -81,3 +81,20 @@ def test_triangular_solve_variants_match_the_oracle(T, n):
         assert np.array_equal(x, x4), variant
         err = np.abs(x - ref).max(axis=1) / np.maximum(np.abs(ref).max(axis=1), 1e-300)
         assert err.max() <= 1e-12, (variant, err.max())
+
+
+def test_fma_rate_kernel_computes_its_chains(T):
+    """The FP64 FMA-rate kernel (the measured reference of the roofline) does the work it is
+    charged for: each lane's sum of its 8 chains x <- x a + b, a = 1 - 2^-20, b = 2^-20, from
+    x0 = 1 + (c + lane mod 8 + 1) 2^-10, equals the closed form 8 + 2^-10 a^k sum_c (c + lane
+    mod 8 + 1) after k steps (the fixed point is exactly 1), to the rounding of k FMAs."""
+    import torch
+    blocks, iters = 3, 1000
+    s = T.design_fma_peak(blocks, iters)
+    torch.cuda.synchronize()
+    got = s.cpu().numpy()
+    lane = np.arange(blocks * 256)
+    a = 1.0 - 2.0 ** -20
+    want = 8.0 + 2.0 ** -10 * a ** iters * np.array([sum(c + (t % 8) + 1 for c in range(8)) for t in lane])
+    assert got.shape == (blocks * 256,)
+    assert np.abs(got - want).max() <= 1e-12 * 8.0
