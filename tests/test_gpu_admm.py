@@ -5,8 +5,12 @@ subproblems to gtol = 1e-10 so that the tolerance of the comparison is set by ro
 not by where inside the 1e-6 ball each solver stops: the branch x then agree to about
 gtol / lambda_min(H) ~ 1e-12, the couplings to ~20x that, and the multipliers (rho = 400)
 to ~1e-8; the test allows 1e-9 on x, 1e-8 on couplings and copies, 1e-6 on multipliers.
-Trajectories over many iterations are not compared (parity unpinned: 1e-6-tolerance
-nonconvex solves make long trajectories sensitive to rounding)."""
+Over 1,000 iterations (branches again to gtol = 1e-10) the two trajectories agree to rounding
+until some branch's trust-region decision lands on a tie that the two roundings resolve
+differently; after that they differ by up to ~1e-5 and the iteration's contraction to its
+fixed point shrinks the difference again. The long-run test holds both regimes to bars
+with margin over what was observed (see its docstring). The per-branch warm-start radii are
+not compared: they differ at values in the thousands, where they never bind a step."""
 import numpy as np
 import pytest
 
@@ -133,4 +137,50 @@ def test_residuals_track_oracle_early(T, net):
     rg = to_np(a.step(5))
     _, ro = oracle.admm_run(net, oracle.admm_init(net), 5)
     assert np.allclose(rg, ro, rtol=1e-5)
+    a.close()
+
+
+def _scale_close(g, o, rel):
+    """|g - o| <= rel * max|o| per field; fields that stay at rounding level (max|o| < 1e-6,
+    the flow-copy multipliers) to 1e-9 absolute."""
+    sc = np.abs(o).max() if o.size else 0.0
+    return np.abs(g - o).max() <= (rel * sc if sc >= 1e-6 else 1e-9) if o.size else True
+
+
+@pytest.mark.parametrize("which", ["200-bus", "2000-bus"])
+def test_trajectory_parity_1000_iterations(T, net, which):
+    """1,000 iterations on the GPU and in the oracle from the same initial state, both solving
+    the branch subproblems to gtol = 1e-10. Observed: every field agrees to ~1e-14 of its
+    scale for the first 100-200 iterations; a tie in one branch's trust-region decision then
+    separates the runs by up to ~1e-5, and by 1,000 iterations the difference has contracted
+    to ~1e-7 in x and ~1e-8 of the multipliers' scale. Bars: after 25 iterations every field
+    within 1e-10 of its scale; over the whole run the residual curves within 2e-3 of their
+    largest value in each of the windows [0,100), [100,300), [300,1000); at 1,000 iterations
+    x, y and the consensus copies within 1e-5, the multipliers within 1e-6 of their scale."""
+    import torch
+    nw = net if which == "200-bus" else W.network()
+    st = oracle.admm_init(nw)
+    a = T.Admm(nw, T.options(gtol=1e-10))
+    a.set_state(torch.from_numpy(st).cuda())
+    r1 = to_np(a.step(25)).reshape(-1, 2)
+    g25 = to_np(a.get_state())
+    o25, q1 = oracle.admm_run(nw, st, 25, gtol=1e-10)
+    gv, ov = oracle.admm_views(nw, g25), oracle.admm_views(nw, o25)
+    for k in ov:
+        if k in ("delta", "alphac"):
+            continue
+        assert _scale_close(np.asarray(gv[k]), np.asarray(ov[k]), 1e-10), (which, 25, k)
+    r2 = to_np(a.step(975)).reshape(-1, 2)
+    g1000 = to_np(a.get_state())
+    o1000, q2 = oracle.admm_run(nw, o25, 975, gtol=1e-10)
+    rg = np.concatenate([r1, r2])
+    ro = np.concatenate([np.asarray(q1).reshape(-1, 2), np.asarray(q2).reshape(-1, 2)])
+    for lo, hi in ((0, 100), (100, 300), (300, 1000)):
+        d = np.abs(rg[lo:hi] - ro[lo:hi]).max(axis=0) / np.abs(ro[lo:hi]).max(axis=0)
+        assert np.all(d <= 2e-3), (which, lo, hi, d)
+    gv, ov = oracle.admm_views(nw, g1000), oracle.admm_views(nw, o1000)
+    for k in ("x", "y", "yt", "pg", "qg", "pgt", "qgt", "wt", "tht"):
+        assert np.abs(np.asarray(gv[k]) - np.asarray(ov[k])).max() <= 1e-5, (which, k)
+    for k in ("lam", "lpg", "lqg", "mu"):
+        assert _scale_close(np.asarray(gv[k]), np.asarray(ov[k]), 1e-6), (which, k)
     a.close()
