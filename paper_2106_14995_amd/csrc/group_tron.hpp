@@ -433,6 +433,10 @@ struct GroupTron {
     MT_INLINE bool chol(uint32_t fm, double alpha)
     {
         MT_UNROLL for (int r = 0; r < R; r++) {
+            // the column loop below sets the reciprocal pivot of rows < N only; a slot past N
+            // (G R > N, e.g. n = 6 on groups of 4 or 8) is an identity row of the factor, and
+            // the substitutions scale every slot, so it needs its 1 here
+            dinv[r] = 1.0;
             const bool fi = bit(fm, row(r));
             MT_UNROLL for (int j = 0; j < N; j++) {
                 const double h = fam.H(*this, r, j);
