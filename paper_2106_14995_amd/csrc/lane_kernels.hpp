@@ -5,6 +5,8 @@
 #include "lane_tron.hpp"
 #include "tron_internal.hpp"
 
+// The largest workgroup a plan selects (64 is the default). The launch bound caps the size
+// the kernel accepts; with one wave per SIMD either way, the register budget is the same.
 constexpr int kLaneBlock = 256;
 
 // Solve instance b in the calling lane.
