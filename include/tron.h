@@ -149,8 +149,11 @@ tron_err tron_batch_create_ex(tron_batch **out, tron_family family, int64_t batc
                               const int32_t *n_host, int32_t n_uniform, const tron_options *opt,
                               const tron_plan_spec *spec, void *stream);
 /* Autotuner: time candidate plans (bucket edge sets, streams, lane/wave split, lane
- * workgroup size) on the caller's own batch, `reps` timed solves each after one warm-up, and
- * return the fastest in *best (and its time per solve in *best_ms). The outputs are written
+ * workgroup size, group widths, the persistent launch) on the caller's own batch, each
+ * captured as a graph (its device time) and replayed `reps` times after the capturing solve
+ * (the fastest replay counts); then the four fastest distinct
+ * candidates are timed again in three interleaved rounds and the lowest median wins; it is
+ * returned in *best (and that median time per solve in *best_ms). The outputs are written
  * by the trial solves. When cache_path is not NULL the result is looked up in / appended to
  * that text file, keyed by the family and the histogram of sizes (a cached entry returns
  * without timing). Errors as tron_batch_create / solve, plus DEVICE for timing failures. */
