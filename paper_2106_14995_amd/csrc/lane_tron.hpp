@@ -3,9 +3,9 @@
 // For small n (n <= 8) every instance lives in one lane of a wave64: x, g, the packed
 // lower triangle of the Hessian, the packed Cholesky factor and the CG vectors are
 // fixed-size arrays indexed only by compile-time constants after unrolling, so they are
-// registers. 64 instances share a wave and 4 waves a CU; there are no cross-lane
-// operations at all (the paper's warp-per-problem reductions, section 5.1, become plain
-// per-lane sums).
+// registers (the branch family alone keeps its 36 parameters in the workgroup's LDS, see
+// BR6T). 64 instances share a wave and 4 waves a CU; there are no cross-lane operations at
+// all (the paper's warp-per-problem reductions, section 5.1, become plain per-lane sums).
 //
 // Algorithm 1 (section 3) per lane, with the readings of the method that the paper leaves
 // to the TRON method it cites:
@@ -20,7 +20,9 @@
 //     alpha = 0 when the diagonal is positive, else a shift grown by doubling (at most 64
 //     tries, then a diagonal factor).
 //   * Steihaug CG on L^-1 A L^-T s = -L^-1 (g + Hs)_F within ||s|| <= delta, at most |F|
-//     iterations; w = L^-T s; projected search with halving (at most 20 halvings);
+//     iterations, or its one exact step when the factorisation needed no shift (then the
+//     preconditioned matrix is the identity); w = L^-T s; projected search with halving (at
+//     most 20 halvings);
 //     another pass while CG ended inside the region and a free variable hit a bound.
 //   * Ratio test and radius update of TRON; the step is measured in the norm of the trust
 //     region that bounded it (||L^T s|| on the last factored free set); when the predicted
