@@ -12,7 +12,9 @@
 // the same bits in every lane of the group, so every decision of the method is taken
 // identically by the group's lanes and a group never diverges from itself. Groups of one
 // wave may take different paths (their own exec masks); a group never leaves its 16-lane
-// DPP row.
+// DPP row. When G does not divide N (n = 6 on 4 or 8 lanes) the last slot of some lanes lies
+// past N: an identity row of the factor (reciprocal pivot 1, set before each factorisation)
+// whose vector entries stay zero.
 //
 // The steps and readings are those of lane_tron.hpp (Algorithm 1 with the TRON ratio test,
 // the step measured in the trust region's norm, the trapezoid reduction near rounding
