@@ -203,3 +203,80 @@ def test_cancel_queued_requests(T):
     assert e.value.code == 5
     srv.result(t3)
     srv.close()
+
+
+def test_random_soak_two_submitters(T):
+    """Two threads submit 60 requests each (sizes drawn from a seed: 1-800 instances, n log-
+    uniform in [2, 96]) to a server with two groups in flight and coalescing, cancelling every
+    seventh right after submission; a third thread collects. Every request ends either with
+    results bitwise equal to the batch API's for the same instances, or, if its cancel came
+    before admission, with the cancellation; nothing stays pending, and the server's device
+    memory returns to zero."""
+    import torch
+    srv = T.Server(W.QP4, hbm_budget=256 << 20, max_inflight=2, streams=2, coalesce=True)
+    lock = threading.Lock()
+    reqs, order, results = {}, [], {}
+    done_submitting = threading.Event()
+
+    def submitter(tid):
+        r = np.random.default_rng(1000 + tid)
+        for k in range(60):
+            B = int(np.exp(r.uniform(0, np.log(800))))
+            bt = mixed(B, 5000 + 100 * tid + k, nmax=96)
+            t = srv.submit_batch(bt)
+            with lock:
+                reqs[t] = bt
+                order.append(t)
+            if k % 7 == 3:
+                try:
+                    srv.cancel(t)
+                except T.TronError:
+                    pass
+
+    def collector():
+        i = 0
+        while True:
+            with lock:
+                t = order[i] if i < len(order) else None
+            if t is None:
+                if done_submitting.is_set():
+                    with lock:
+                        if i >= len(order):
+                            return
+                    continue
+                time.sleep(0.001)
+                continue
+            srv.wait(t, 30.0)
+            try:
+                results[t] = srv.result(t)
+            except T.TronError as e:
+                assert "cancel" in str(e), e
+                results[t] = None
+            i += 1
+
+    subs = [threading.Thread(target=submitter, args=(i,)) for i in range(2)]
+    col = threading.Thread(target=collector)
+    col.start()
+    for th in subs:
+        th.start()
+    for th in subs:
+        th.join()
+    done_submitting.set()
+    col.join(120)
+    assert not col.is_alive()
+    assert set(results) == set(reqs)
+    assert srv.stats()["device_bytes"] == 0
+    srv.close()
+    checked = 0
+    for t, res in results.items():
+        if res is None:
+            continue
+        bt = reqs[t]
+        h = T.Batch(W.QP4, bt.n)
+        x, f, st, it = h.solve(*T.to_device(bt))
+        torch.cuda.synchronize()
+        assert np.array_equal(x.cpu().numpy(), res["x"]) and np.array_equal(f.cpu().numpy(), res["f"]), t
+        assert np.array_equal(st.cpu().numpy(), res["status"]), t
+        h.close()
+        checked += 1
+    assert checked >= 100
