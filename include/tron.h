@@ -132,7 +132,9 @@ typedef struct {
     int32_t pool_waves;   /* 0 (bucketed), 8 or 12 (persistent)                                */
     int32_t lane_group;   /* lanes per instance for n <= lane_max_n: 1 (lane kernel), 2, 4 or 8
                              (the group kernel: one instance per group of lanes, rows split
-                             over the group, section 4.2's thread configuration)             */
+                             over the group, section 4.2's thread configuration), or 0:
+                             automatic, 8 for a uniform quartic batch with n = 7 or 8 of at
+                             most 16,384 instances (where it is the faster), else 1          */
     int32_t group16;      /* 0, 8 or 16: instances with lane_max_n < n <= 16 go to the group
                              kernel of that width instead of the wavefront kernel            */
     int32_t wave_global;  /* 1: quartic-family wavefront buckets up to n = 128 keep the Hessian
@@ -141,7 +143,7 @@ typedef struct {
 } tron_plan_spec;
 
 /* lane_max_n 8, edges 16/24/32/40/48/56/64/80/96/112/128, 4 streams, lane_block 64,
- * pool_waves 0, lane_group 1, group16 0, wave_global 0. */
+ * pool_waves 0, lane_group 0 (automatic), group16 0, wave_global 0. */
 void tron_default_plan_spec(tron_plan_spec *spec);
 /* tron_batch_create with an explicit plan (spec NULL = default). INVALID for a bad spec,
  * UNSUPPORTED when some n exceeds the largest edge. */
