@@ -1,20 +1,25 @@
 // admm.hip -- the component ADMM of the power-flow application (section 6.1) on the GPU.
 //
 // One iteration, in the order the paper gives (generators and branches, then buses, then
-// multipliers), is six kernels on one stream:
-//   gen_pack   generator updates (closed form) and the BR6 parameter blocks of the branches
-//   lane_kernel<BR6>  batched branch solves, warm-started in place from the resident x,
-//              radius and Cauchy step length
-//   couplings  branch couplings y = (p_ij q_ij p_ji q_ji v_i^2 v_j^2 th_i th_j) at the new x
+// multipliers), is three kernels on one stream:
+//   branch     per branch (one lane each): its BR6 parameter block gathered from the state
+//              into the workgroup's LDS, the batched branch solve warm-started in place
+//              from the resident x, radius and Cauchy step length, then the branch
+//              couplings y = (p_ij q_ij p_ji q_ji v_i^2 v_j^2 th_i th_j) at the new x;
+//              one more workgroup reduces the previous iteration's residual parts
 //   buses      per bus: weighted projection of the targets onto the two balance equations
 //              (a 2 x 2 solve), new copies for its generators and branch ends, and the
 //              squared change of those copies (dual residual part)
-//   duals      multiplier updates and the squared primal residual parts
-//   reduce     one workgroup sums the parts in a fixed order (deterministic) into the
-//              residual norms of the iteration
-// The state stays on the device in the flat layout of include/tron.h; the host only
-// launches. The closed forms are the exact minimisers of the augmented Lagrangians of the
-// generator and bus subproblems (the paper states only that they exist).
+//   duals      multiplier updates and the squared primal residual parts; then the
+//              generator updates (closed form) of the next iteration, whose inputs are all
+//              final at this point
+// The residual norms of an iteration sum its parts in a fixed order (deterministic); the
+// last iteration of a call reduces them in a kernel of its own (reduce).
+// The first iteration of each call updates the generators in a kernel of its own, so that
+// the state between calls is the same as with the generator update at the top of every
+// iteration. The state stays on the device in the flat layout of include/tron.h; the host
+// only launches. The closed forms are the exact minimisers of the augmented Lagrangians of
+// the generator and bus subproblems (the paper states only that they exist).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -109,43 +114,112 @@ __global__ __launch_bounds__(kBlock) void admm_init_kernel(Net n, double *s)
     }
 }
 
-// generator updates and branch parameter blocks (both read only the previous copies)
-__global__ __launch_bounds__(kBlock) void gen_pack_kernel(Net n, double *s, double *prm)
+// generator update (closed form) from the previous copies and multipliers
+__device__ inline void gen_update(const Net &n, const View &v, int64_t t)
+{
+    const double rho = n.rho;
+    const double c2 = n.base * n.base * n.cost[2 * t], c1 = n.base * n.cost[2 * t + 1];
+    const double *lim = n.glim + 4 * t;
+    const double p = (rho * v.pgt[t] - v.lpg[t] - c1) / (2.0 * c2 + rho);
+    const double q = v.qgt[t] - v.lqg[t] / rho;
+    v.pg[t] = clampd(p, lim[0], lim[1]);
+    v.qg[t] = clampd(q, lim[2], lim[3]);
+}
+
+__global__ __launch_bounds__(kBlock) void gen_kernel(Net n, double *s)
 {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    View v = split(s, n.G, n.L, n.B);
-    const double rho = n.rho;
-    if (t < n.G) {
-        const double c2 = n.base * n.base * n.cost[2 * t], c1 = n.base * n.cost[2 * t + 1];
-        const double *lim = n.glim + 4 * t;
-        const double p = (rho * v.pgt[t] - v.lpg[t] - c1) / (2.0 * c2 + rho);
-        const double q = v.qgt[t] - v.lqg[t] / rho;
-        v.pg[t] = clampd(p, lim[0], lim[1]);
-        v.qg[t] = clampd(q, lim[2], lim[3]);
-    } else if (t < (int64_t)n.G + n.L) {
-        const int64_t l = t - n.G;
-        const int i = n.br_from[l], j = n.br_to[l];
-        double *p = prm + 36 * l;
-        for (int k = 0; k < 8; k++) p[k] = n.adm[8 * l + k];
-        for (int k = 0; k < 4; k++) p[8 + k] = v.yt[4 * l + k];
-        p[12] = v.wt[i];
-        p[13] = v.wt[j];
-        p[14] = v.tht[i];
-        p[15] = v.tht[j];
-        for (int k = 0; k < 8; k++) p[16 + k] = v.lam[8 * l + k];
-        p[24] = v.mu[2 * l];
-        p[25] = v.mu[2 * l + 1];
-        for (int k = 0; k < 10; k++) p[26 + k] = rho;
+    if (t < n.G) gen_update(n, split(s, n.G, n.L, n.B), t);
+}
+
+constexpr int kReduce = 1024;
+
+// Residual norms from the parts: kReduce partial sums with fixed strides (sum over k = t,
+// t + kReduce, ...) combined by a fixed halving tree, so the result is deterministic.
+// reduce_kernel runs it with kReduce threads; reduce_parts64 with one 64-lane workgroup
+// that takes the kReduce positions 64 at a time: the same additions in the same order.
+__device__ void reduce_parts64(const double *part_primal, int64_t np, const double *part_dual, int64_t nd,
+                               double rho, double *resid)
+{
+    __shared__ double sp[kReduce], sd[kReduce];
+    const int t = threadIdx.x;
+    for (int m = 0; m < kReduce / kBlock; m++) {
+        const int tv = t + kBlock * m;
+        double a = 0.0, b = 0.0;
+        for (int64_t k = tv; k < np; k += kReduce) a += part_primal[k];
+        for (int64_t k = tv; k < nd; k += kReduce) b += part_dual[k];
+        sp[tv] = a;
+        sd[tv] = b;
+    }
+    __syncthreads();
+    for (int w = kReduce / 2; w > 0; w >>= 1) {
+        for (int m = 0; m < kReduce / kBlock; m++) {
+            const int tv = t + kBlock * m;
+            if (tv < w) {
+                sp[tv] += sp[tv + w];
+                sd[tv] += sd[tv + w];
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        resid[0] = sqrt(sp[0]);
+        resid[1] = rho * sqrt(sd[0]);
     }
 }
 
-__global__ __launch_bounds__(kBlock) void couplings_kernel(Net n, double *s)
+// Branch l in the calling lane: its parameter block (in the order of include/tron.h: the
+// admittances, the flow targets, the w and theta targets of both ends, the multipliers of
+// the eight couplings and of the two flow copies, the penalty of each coupling) is formed
+// from the previous copies and multipliers straight into the workgroup's LDS, where the BR6
+// family keeps it; the solve is the batch API's BR6 lane solve, warm-started from the
+// resident x, radius and Cauchy step length; the couplings at the new x follow.
+// Outputs: x, radius and Cauchy step in the state, f, status and iterations per branch.
+// With prev_resid, one workgroup past the branches' reduces the residual parts the previous
+// iteration's bus and multiplier kernels left (nothing writes them before this kernel ends).
+__global__ __launch_bounds__(kBlock) void branch_kernel(Net n, double *s, mt::Options opt, double *fo,
+                                                        int32_t *status, int32_t *iters,
+                                                        const double *part_primal, const double *part_dual,
+                                                        double *prev_resid)
 {
+    if (blockIdx.x == (n.L + kBlock - 1) / kBlock) {
+        reduce_parts64(part_primal, (int64_t)n.G + n.L, part_dual, n.B, n.rho, prev_resid);
+        return;
+    }
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (l >= n.L) return;
     View v = split(s, n.G, n.L, n.B);
+    const double rho = n.rho;
+    const int i = n.br_from[l], j = n.br_to[l];
+    double p[36];
+    for (int k = 0; k < 8; k++) p[k] = n.adm[8 * l + k];
+    for (int k = 0; k < 4; k++) p[8 + k] = v.yt[4 * l + k];
+    p[12] = v.wt[i];
+    p[13] = v.wt[j];
+    p[14] = v.tht[i];
+    p[15] = v.tht[j];
+    for (int k = 0; k < 8; k++) p[16 + k] = v.lam[8 * l + k];
+    p[24] = v.mu[2 * l];
+    p[25] = v.mu[2 * l + 1];
+    for (int k = 0; k < 10; k++) p[26 + k] = rho;
+    mt::LaneTron<mt::BR6, 6> st;
+    st.fam.load(p, 6);
+    double *x = v.x + 6 * l;
+    const double *lo = n.blo + 6 * l, *hi = n.bhi + 6 * l;
+    MT_UNROLL for (int k = 0; k < 6; k++) {
+        st.lo[k] = lo[k];
+        st.hi[k] = hi[k];
+        st.x[k] = x[k];
+    }
+    const int32_t rc = st.solve(opt, v.del[l], v.alp[l]);
+    MT_UNROLL for (int k = 0; k < 6; k++) x[k] = st.x[k];
+    fo[l] = st.f;
+    status[l] = rc;
+    iters[l] = st.iters;
+    v.del[l] = st.delta;
+    v.alp[l] = st.alphac;
     double y[8];
-    couplings(n.adm + 8 * l, v.x + 6 * l, y);
+    couplings(n.adm + 8 * l, st.x, y);
     for (int k = 0; k < 8; k++) v.y[8 * l + k] = y[k];
 }
 
@@ -305,8 +379,9 @@ __global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *p
     part_dual[b] = d2;
 }
 
-// multipliers: lam += rho (y - yt) for every coupling, mu += rho (z - p)
-__global__ __launch_bounds__(kBlock) void duals_kernel(Net n, double *s, double *part_primal)
+// multipliers: lam += rho (y - yt) for every coupling, mu += rho (z - p); with gen_next, the
+// generator update of the next iteration (its copies and multipliers are final here)
+__global__ __launch_bounds__(kBlock) void duals_kernel(Net n, double *s, double *part_primal, int gen_next)
 {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     View v = split(s, n.G, n.L, n.B);
@@ -316,6 +391,7 @@ __global__ __launch_bounds__(kBlock) void duals_kernel(Net n, double *s, double 
         v.lpg[t] += rho * rp;
         v.lqg[t] += rho * rq;
         part_primal[t] = rp * rp + rq * rq;
+        if (gen_next) gen_update(n, v, t);
     } else if (t < (int64_t)n.G + n.L) {
         const int64_t l = t - n.G;
         const int i = n.br_from[l], j = n.br_to[l];
@@ -334,9 +410,7 @@ __global__ __launch_bounds__(kBlock) void duals_kernel(Net n, double *s, double 
     }
 }
 
-constexpr int kReduce = 1024;
-
-// one workgroup: fixed per-thread strides and a fixed tree, so the result is deterministic
+// one workgroup of kReduce threads (see reduce_parts64)
 __global__ __launch_bounds__(kReduce) void reduce_kernel(const double *part_primal, int64_t np,
                                                          const double *part_dual, int64_t nd,
                                                          double rho, double *resid)
@@ -372,7 +446,7 @@ struct admm {
     tron_options opt{};
     int64_t state_size = 0;
     double *d_state = nullptr;
-    double *d_prm = nullptr, *d_f = nullptr, *d_part = nullptr;
+    double *d_f = nullptr, *d_part = nullptr;
     int32_t *d_status = nullptr, *d_iters = nullptr;
     std::vector<void *> owned;
 };
@@ -413,7 +487,6 @@ extern "C" tron_err admm_create(admm **out, const admm_network *n, const tron_op
         (n->ngen > 0 && (!n->gen_bus || !n->gen_cost || !n->gen_lim)))
         return mt_fail(TRON_ERR_INVALID, "null network array");
     if (!(n->rho > 0.0)) return mt_fail(TRON_ERR_INVALID, "rho must be positive");
-    mt_prepare_br6();
     const int G = n->ngen, L = n->nbranch, B = n->nbus;
     // adjacency in increasing index order
     std::vector<int32_t> gptr(B + 1, 0), eptr(B + 1, 0);
@@ -468,7 +541,6 @@ extern "C" tron_err admm_create(admm **out, const admm_network *n, const tron_op
     UP(p_eidx, eidx.data(), 2 * (size_t)L);
     a->state_size = admm_state_size(n);
     UP(a->d_state, (const double *)nullptr, (size_t)a->state_size);
-    UP(a->d_prm, (const double *)nullptr, 36 * (size_t)L);
     UP(a->d_f, (const double *)nullptr, (size_t)L);
     UP(a->d_part, (const double *)nullptr, (size_t)G + L + B);
     UP(a->d_status, (const int32_t *)nullptr, (size_t)L);
@@ -491,41 +563,33 @@ extern "C" tron_err admm_step(admm *a, int32_t iters, double *d_resid, void *str
     if (!a || iters < 0) return mt_fail(TRON_ERR_INVALID, "bad argument");
     hipStream_t st = (hipStream_t)stream;
     const Net &n = a->net;
-    View v = split(a->d_state, n.G, n.L, n.B);
-    LaneArgs la{};
-    la.params = a->d_prm;
-    la.lo = n.blo;
-    la.hi = n.bhi;
-    la.x0 = v.x;
-    la.x = v.x;
-    la.f = a->d_f;
-    la.status = a->d_status;
-    la.iters = a->d_iters;
-    la.state = v.del;  // radius then Cauchy step length, contiguous in the state
-    la.ts = nullptr;
-    la.count = n.L;
-    la.batch = n.L;
-    la.n_uniform = 6;
-    la.psize = 36;
-    la.opt.gtol = a->opt.gtol;
-    la.opt.cg_rtol = a->opt.cg_rtol;
-    la.opt.delta0 = a->opt.delta0;
-    la.opt.max_iter = a->opt.max_iter;
-    la.opt.warm = 1;
-    la.lane_block = 64;  // a few thousand branches: one wave per workgroup, spread over more CUs
+    mt::Options opt{};
+    opt.gtol = a->opt.gtol;
+    opt.cg_rtol = a->opt.cg_rtol;
+    opt.delta0 = a->opt.delta0;
+    opt.max_iter = a->opt.max_iter;
+    opt.warm = 1;
+    // branch lanes in 64-lane workgroups: a few thousand branches, one wave per workgroup,
+    // spread over more CUs; each wave's parameter blocks take 36 x 64 doubles of LDS
+    const size_t lds = sizeof(double) * mt::BR6::kLdsDoubles * kBlock;
     double *part_primal = a->d_part, *part_dual = a->d_part + n.G + n.L;
     for (int32_t it = 0; it < iters; it++) {
-        hipLaunchKernelGGL(gen_pack_kernel, dim3(grid_for((int64_t)n.G + n.L)), dim3(kBlock), 0, st, n,
-                           a->d_state, a->d_prm);
-        mt_launch_br6(la, st);
-        hipLaunchKernelGGL(couplings_kernel, dim3(grid_for(n.L)), dim3(kBlock), 0, st, n, a->d_state);
+        if (it == 0 && n.G > 0)
+            hipLaunchKernelGGL(gen_kernel, dim3(grid_for(n.G)), dim3(kBlock), 0, st, n, a->d_state);
+        // the previous iteration's residuals are reduced by one more workgroup of this launch
+        double *prev = (it > 0 && d_resid) ? d_resid + 2 * (int64_t)(it - 1) : nullptr;
+        hipLaunchKernelGGL(branch_kernel, dim3(grid_for(n.L) + (prev ? 1u : 0u)), dim3(kBlock), lds, st, n,
+                           a->d_state, opt, a->d_f, a->d_status, a->d_iters, (const double *)part_primal,
+                           (const double *)part_dual, prev);
         hipLaunchKernelGGL(bus_kernel, dim3(grid_for(n.B)), dim3(kBlock), 0, st, n, a->d_state, part_dual);
         hipLaunchKernelGGL(duals_kernel, dim3(grid_for((int64_t)n.G + n.L)), dim3(kBlock), 0, st, n,
-                           a->d_state, part_primal);
-        hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kReduce), 0, st, part_primal,
-                           (int64_t)n.G + n.L, part_dual, (int64_t)n.B, n.rho,
-                           d_resid ? d_resid + 2 * (int64_t)it : nullptr);
+                           a->d_state, part_primal, (int)(it + 1 < iters));
     }
+    // the last iteration's residuals
+    if (iters > 0 && d_resid)
+        hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kReduce), 0, st, (const double *)part_primal,
+                           (int64_t)n.G + n.L, (const double *)part_dual, (int64_t)n.B, n.rho,
+                           d_resid + 2 * (int64_t)(iters - 1));
     HIP_TRY(hipGetLastError());
     return TRON_OK;
 }

@@ -131,6 +131,28 @@ def test_checkpoint_resume_bitwise(T, net):
     assert np.array_equal(r_all, np.concatenate([r1, r2]))
 
 
+def test_single_iteration_calls_match_one_call(T, net):
+    """Twelve calls of one iteration against one call of twelve: the first iteration of a
+    call updates the generators in a kernel of its own, later ones inside the previous
+    iteration's multiplier kernel, and the residual norms come from whichever workgroup of
+    that kernel finishes last. State and residuals agree bitwise."""
+    a = T.Admm(net)
+    r_one = to_np(a.step(12))
+    s_one = to_np(a.get_state())
+    a.close()
+    b = T.Admm(net)
+    r_each = np.concatenate([to_np(b.step(1)) for _ in range(12)])
+    s_each = to_np(b.get_state())
+    b.close()
+    c = T.Admm(net)
+    assert T.lib().admm_step(c._h, 12, None, None) == 0  # no residuals asked for
+    s_none = to_np(c.get_state())
+    c.close()
+    assert np.array_equal(s_one, s_each)
+    assert np.array_equal(r_one, r_each)
+    assert np.array_equal(s_one, s_none)
+
+
 def test_residuals_track_oracle_early(T, net):
     """Diagnostic agreement of the first iterations' residuals (not a pinned parity)."""
     a = T.Admm(net)
