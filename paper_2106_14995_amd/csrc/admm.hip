@@ -1,20 +1,20 @@
 // admm.hip -- the component ADMM of the power-flow application (section 6.1) on the GPU.
 //
 // One iteration, in the order the paper gives (generators and branches, then buses, then
-// multipliers), is three kernels on one stream:
+// multipliers), is two kernels on one stream:
 //   branch     per branch (one lane each): its BR6 parameter block gathered from the state
 //              into the workgroup's LDS, the batched branch solve warm-started in place
 //              from the resident x, radius and Cauchy step length, then the branch
 //              couplings y = (p_ij q_ij p_ji q_ji v_i^2 v_j^2 th_i th_j) at the new x;
 //              one more workgroup reduces the previous iteration's residual parts
 //   buses      per bus: weighted projection of the targets onto the two balance equations
-//              (a 2 x 2 solve), new copies for its generators and branch ends, and the
-//              squared change of those copies (dual residual part)
-//   duals      multiplier updates and the squared primal residual parts; then the
-//              generator updates (closed form) of the next iteration, whose inputs are all
-//              final at this point
-// The residual norms of an iteration sum its parts in a fixed order (deterministic); the
-// last iteration of a call reduces them in a kernel of its own (reduce).
+//              (a 2 x 2 solve) giving new copies for its generators and branch ends, then
+//              the multiplier steps of the couplings those copies belong to (each coupling
+//              has its copy at exactly one bus), then the generator updates (closed form)
+//              of the next iteration, whose inputs are all final at this point; per bus the
+//              squared primal residuals and the squared changes of its copies
+// The residual norms of an iteration sum the per-bus parts in a fixed order (deterministic);
+// the last iteration of a call reduces them in a kernel of its own (reduce).
 // The first iteration of each call updates the generators in a kernel of its own, so that
 // the state between calls is the same as with the generator update at the top of every
 // iteration. The state stays on the device in the flat layout of include/tron.h; the host
@@ -114,14 +114,15 @@ __global__ __launch_bounds__(kBlock) void admm_init_kernel(Net n, double *s)
     }
 }
 
-// generator update (closed form) from the previous copies and multipliers
-__device__ inline void gen_update(const Net &n, const View &v, int64_t t)
+// generator update (closed form) from its copies and multipliers
+__device__ inline void gen_update(const Net &n, const View &v, int64_t t, double pgt, double qgt, double lpg,
+                                  double lqg)
 {
     const double rho = n.rho;
     const double c2 = n.base * n.base * n.cost[2 * t], c1 = n.base * n.cost[2 * t + 1];
     const double *lim = n.glim + 4 * t;
-    const double p = (rho * v.pgt[t] - v.lpg[t] - c1) / (2.0 * c2 + rho);
-    const double q = v.qgt[t] - v.lqg[t] / rho;
+    const double p = (rho * pgt - lpg - c1) / (2.0 * c2 + rho);
+    const double q = qgt - lqg / rho;
     v.pg[t] = clampd(p, lim[0], lim[1]);
     v.qg[t] = clampd(q, lim[2], lim[3]);
 }
@@ -129,7 +130,9 @@ __device__ inline void gen_update(const Net &n, const View &v, int64_t t)
 __global__ __launch_bounds__(kBlock) void gen_kernel(Net n, double *s)
 {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t < n.G) gen_update(n, split(s, n.G, n.L, n.B), t);
+    if (t >= n.G) return;
+    const View v = split(s, n.G, n.L, n.B);
+    gen_update(n, v, t, v.pgt[t], v.qgt[t], v.lpg[t], v.lqg[t]);
 }
 
 constexpr int kReduce = 1024;
@@ -176,14 +179,14 @@ __device__ void reduce_parts64(const double *part_primal, int64_t np, const doub
 // resident x, radius and Cauchy step length; the couplings at the new x follow.
 // Outputs: x, radius and Cauchy step in the state, f, status and iterations per branch.
 // With prev_resid, one workgroup past the branches' reduces the residual parts the previous
-// iteration's bus and multiplier kernels left (nothing writes them before this kernel ends).
+// iteration's bus kernel left (nothing writes them before this kernel ends).
 __global__ __launch_bounds__(kBlock) void branch_kernel(Net n, double *s, mt::Options opt, double *fo,
                                                         int32_t *status, int32_t *iters,
                                                         const double *part_primal, const double *part_dual,
                                                         double *prev_resid)
 {
     if (blockIdx.x == (n.L + kBlock - 1) / kBlock) {
-        reduce_parts64(part_primal, (int64_t)n.G + n.L, part_dual, n.B, n.rho, prev_resid);
+        reduce_parts64(part_primal, n.B, part_dual, n.B, n.rho, prev_resid);
         return;
     }
     const int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -226,12 +229,17 @@ __global__ __launch_bounds__(kBlock) void branch_kernel(Net n, double *s, mt::Op
 // bus subproblem: minimise sum w_k/2 (yt_k - t_k)^2, t_k = y_k + lam_k / rho, over the bus
 // copies (generator powers, branch-end flows, w shared by the ends, theta), subject to
 // the two balance rows; yt = t - W^-1 A' (A W^-1 A')^-1 (A t - b)
+// Then the multiplier steps of the couplings whose copies the bus holds (each coupling
+// belongs to one bus: a generator's powers, a branch end's flows, w and theta, and the flow
+// copy z of the end's p): lam += rho (y - yt), mu += rho (z - p); with gen_next, the
+// generator update of the next iteration from the new copies and multipliers.
 // One thread per bus. The state was just written by kernels running on every XCD, so most
 // loads miss this XCD's L2 and each round of dependent loads costs about a microsecond. A bus
 // with at most kFastG generators and kFastE branch ends therefore loads everything it needs
 // in three rounds (its own data and CSR bounds; the neighbour indices; every neighbour value
 // both passes use) and keeps it in registers; larger buses take the general path. Both paths
-// perform the same operations in the same order.
+// perform the same operations in the same order. Residual parts per bus: the squared
+// primal residuals of its couplings and the squared changes of its copies.
 constexpr int kFastG = 4, kFastE = 16;
 
 struct BusSums {
@@ -263,7 +271,40 @@ __device__ inline BusSolve bus_solve(const Net &n, int64_t b, const BusSums &t, 
     return r;
 }
 
-__global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *part_dual)
+// generator g of the bus after its new copies (np, nq): multipliers, primal residual part,
+// and with gen_next its next update
+__device__ inline void gen_duals(const Net &n, const View &v, int g, double pg, double qg, double lpg, double lqg,
+                                 double np, double nq, int gen_next, double &p2)
+{
+    const double rho = n.rho;
+    const double rp = pg - np, rq = qg - nq;
+    const double lp = lpg + rho * rp, lq = lqg + rho * rq;
+    v.lpg[g] = lp;
+    v.lqg[g] = lq;
+    p2 += rp * rp + rq * rq;
+    if (gen_next) gen_update(n, v, g, np, nq, lp, lq);
+}
+
+// end e of branch l after the bus's new copies (np, nq, wnew, tnew): the multipliers of the
+// end's four couplings (y: its p, q, w, theta; la: their multipliers), the flow copy's
+// multiplier mu (z: the flow copy x[4 + e]), and the primal residual part
+__device__ inline void end_duals(const Net &n, const View &v, int64_t l, int e, const double (&y)[4],
+                                 const double (&la)[4], double z, double mu, double np, double nq, double wnew,
+                                 double tnew, double &p2)
+{
+    const double rho = n.rho;
+    const double r0 = y[0] - np, r1 = y[1] - nq, r2 = y[2] - wnew, r3 = y[3] - tnew;
+    double *lam = v.lam + 8 * l;
+    lam[2 * e] = la[0] + rho * r0;
+    lam[2 * e + 1] = la[1] + rho * r1;
+    lam[4 + e] = la[2] + rho * r2;
+    lam[6 + e] = la[3] + rho * r3;
+    v.mu[2 * l + e] = mu + rho * (z - y[0]);
+    p2 += r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3;
+}
+
+__global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *part_primal, double *part_dual,
+                                                     int gen_next)
 {
     const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (b >= n.B) return;
@@ -276,7 +317,7 @@ __global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *p
     const double wt0 = v.wt[b], tht0 = v.tht[b];
     const int ng = g1 - g0, ne = e1 - e0;
     BusSums t;
-    double d2 = 0.0;
+    double d2 = 0.0, p2 = 0.0;
     if (ng <= kFastG && ne <= kFastE) {
         int gi[kFastG], code[kFastE];
         MT_UNROLL for (int u = 0; u < kFastG; u++) gi[u] = u < ng ? n.bg_idx[g0 + u] : -1;
@@ -288,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *p
             pgt[u] = v.pgt[g]; qgt[u] = v.qgt[g];
         }
         double yp[kFastE], yq[kFastE], yw[kFastE], yth[kFastE], lp[kFastE], lq[kFastE], lw[kFastE], lth[kFastE];
-        double otp[kFastE], otq[kFastE];
+        double otp[kFastE], otq[kFastE], z[kFastE], mu[kFastE];
         MT_UNROLL for (int u = 0; u < kFastE; u++) {
             const int c = code[u] < 0 ? 0 : code[u];
             const int64_t l = c >> 1;
@@ -297,6 +338,7 @@ __global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *p
             yp[u] = y[2 * e]; yq[u] = y[2 * e + 1]; yw[u] = y[4 + e]; yth[u] = y[6 + e];
             lp[u] = la[2 * e]; lq[u] = la[2 * e + 1]; lw[u] = la[4 + e]; lth[u] = la[6 + e];
             otp[u] = yt[2 * e]; otq[u] = yt[2 * e + 1];
+            z[u] = v.x[6 * l + 4 + e]; mu[u] = v.mu[2 * l + e];
         }
         MT_UNROLL for (int u = 0; u < kFastG; u++)
             if (u < ng) {
@@ -318,6 +360,7 @@ __global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *p
                 d2 += (np - pgt[u]) * (np - pgt[u]) + (nq - qgt[u]) * (nq - qgt[u]);
                 v.pgt[gi[u]] = np;
                 v.qgt[gi[u]] = nq;
+                gen_duals(n, v, gi[u], pg[u], qg[u], lpg[u], lqg[u], np, nq, gen_next, p2);
             }
         const double dw = r.wnew - wt0, dt = r.tnew - tht0;
         MT_UNROLL for (int u = 0; u < kFastE; u++)
@@ -331,6 +374,8 @@ __global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *p
                 double *yt = v.yt + 4 * l;
                 yt[2 * e] = np;
                 yt[2 * e + 1] = nq;
+                const double ye[4] = {yp[u], yq[u], yw[u], yth[u]}, le[4] = {lp[u], lq[u], lw[u], lth[u]};
+                end_duals(n, v, l, e, ye, le, z[u], mu[u], np, nq, r.wnew, r.tnew, p2);
             }
         v.wt[b] = r.wnew;
         v.tht[b] = r.tnew;
@@ -353,11 +398,13 @@ __global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *p
         const BusSolve r = bus_solve(n, b, t, ng, ne, ld);
         for (int k = g0; k < g1; k++) {
             const int g = n.bg_idx[k];
-            const double np = v.pg[g] + v.lpg[g] / rho - r.up / rho;
-            const double nq = v.qg[g] + v.lqg[g] / rho - r.uq / rho;
+            const double pg = v.pg[g], qg = v.qg[g], lpg = v.lpg[g], lqg = v.lqg[g];
+            const double np = pg + lpg / rho - r.up / rho;
+            const double nq = qg + lqg / rho - r.uq / rho;
             d2 += (np - v.pgt[g]) * (np - v.pgt[g]) + (nq - v.qgt[g]) * (nq - v.qgt[g]);
             v.pgt[g] = np;
             v.qgt[g] = nq;
+            gen_duals(n, v, g, pg, qg, lpg, lqg, np, nq, gen_next, p2);
         }
         const double dw = r.wnew - wt0, dt = r.tnew - tht0;
         for (int k = e0; k < e1; k++) {
@@ -366,48 +413,21 @@ __global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *p
             const int e = code & 1;
             const double *y = v.y + 8 * l, *la = v.lam + 8 * l;
             double *yt = v.yt + 4 * l;
-            const double np = y[2 * e] + la[2 * e] / rho + r.up / rho;
-            const double nq = y[2 * e + 1] + la[2 * e + 1] / rho + r.uq / rho;
+            const double ye[4] = {y[2 * e], y[2 * e + 1], y[4 + e], y[6 + e]};
+            const double le[4] = {la[2 * e], la[2 * e + 1], la[4 + e], la[6 + e]};
+            const double np = ye[0] + le[0] / rho + r.up / rho;
+            const double nq = ye[1] + le[1] / rho + r.uq / rho;
             d2 += (np - yt[2 * e]) * (np - yt[2 * e]) + (nq - yt[2 * e + 1]) * (nq - yt[2 * e + 1]);
             d2 += dw * dw + dt * dt;
             yt[2 * e] = np;
             yt[2 * e + 1] = nq;
+            end_duals(n, v, l, e, ye, le, v.x[6 * l + 4 + e], v.mu[2 * l + e], np, nq, r.wnew, r.tnew, p2);
         }
         v.wt[b] = r.wnew;
         v.tht[b] = r.tnew;
     }
+    part_primal[b] = p2;
     part_dual[b] = d2;
-}
-
-// multipliers: lam += rho (y - yt) for every coupling, mu += rho (z - p); with gen_next, the
-// generator update of the next iteration (its copies and multipliers are final here)
-__global__ __launch_bounds__(kBlock) void duals_kernel(Net n, double *s, double *part_primal, int gen_next)
-{
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    View v = split(s, n.G, n.L, n.B);
-    const double rho = n.rho;
-    if (t < n.G) {
-        const double rp = v.pg[t] - v.pgt[t], rq = v.qg[t] - v.qgt[t];
-        v.lpg[t] += rho * rp;
-        v.lqg[t] += rho * rq;
-        part_primal[t] = rp * rp + rq * rq;
-        if (gen_next) gen_update(n, v, t);
-    } else if (t < (int64_t)n.G + n.L) {
-        const int64_t l = t - n.G;
-        const int i = n.br_from[l], j = n.br_to[l];
-        const double *y = v.y + 8 * l, *yt = v.yt + 4 * l, *x = v.x + 6 * l;
-        double *la = v.lam + 8 * l;
-        const double copy[8] = {yt[0], yt[1], yt[2], yt[3], v.wt[i], v.wt[j], v.tht[i], v.tht[j]};
-        double p2 = 0.0;
-        for (int k = 0; k < 8; k++) {
-            const double r = y[k] - copy[k];
-            la[k] += rho * r;
-            p2 += r * r;
-        }
-        v.mu[2 * l] += rho * (x[4] - y[0]);
-        v.mu[2 * l + 1] += rho * (x[5] - y[2]);
-        part_primal[t] = p2;
-    }
 }
 
 // one workgroup of kReduce threads (see reduce_parts64)
@@ -542,7 +562,7 @@ extern "C" tron_err admm_create(admm **out, const admm_network *n, const tron_op
     a->state_size = admm_state_size(n);
     UP(a->d_state, (const double *)nullptr, (size_t)a->state_size);
     UP(a->d_f, (const double *)nullptr, (size_t)L);
-    UP(a->d_part, (const double *)nullptr, (size_t)G + L + B);
+    UP(a->d_part, (const double *)nullptr, 2 * (size_t)B);
     UP(a->d_status, (const int32_t *)nullptr, (size_t)L);
     UP(a->d_iters, (const int32_t *)nullptr, (size_t)L);
 #undef UP
@@ -572,7 +592,7 @@ extern "C" tron_err admm_step(admm *a, int32_t iters, double *d_resid, void *str
     // branch lanes in 64-lane workgroups: a few thousand branches, one wave per workgroup,
     // spread over more CUs; each wave's parameter blocks take 36 x 64 doubles of LDS
     const size_t lds = sizeof(double) * mt::BR6::kLdsDoubles * kBlock;
-    double *part_primal = a->d_part, *part_dual = a->d_part + n.G + n.L;
+    double *part_primal = a->d_part, *part_dual = a->d_part + n.B;
     for (int32_t it = 0; it < iters; it++) {
         if (it == 0 && n.G > 0)
             hipLaunchKernelGGL(gen_kernel, dim3(grid_for(n.G)), dim3(kBlock), 0, st, n, a->d_state);
@@ -581,14 +601,13 @@ extern "C" tron_err admm_step(admm *a, int32_t iters, double *d_resid, void *str
         hipLaunchKernelGGL(branch_kernel, dim3(grid_for(n.L) + (prev ? 1u : 0u)), dim3(kBlock), lds, st, n,
                            a->d_state, opt, a->d_f, a->d_status, a->d_iters, (const double *)part_primal,
                            (const double *)part_dual, prev);
-        hipLaunchKernelGGL(bus_kernel, dim3(grid_for(n.B)), dim3(kBlock), 0, st, n, a->d_state, part_dual);
-        hipLaunchKernelGGL(duals_kernel, dim3(grid_for((int64_t)n.G + n.L)), dim3(kBlock), 0, st, n,
-                           a->d_state, part_primal, (int)(it + 1 < iters));
+        hipLaunchKernelGGL(bus_kernel, dim3(grid_for(n.B)), dim3(kBlock), 0, st, n, a->d_state, part_primal,
+                           part_dual, (int)(it + 1 < iters));
     }
     // the last iteration's residuals
     if (iters > 0 && d_resid)
         hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kReduce), 0, st, (const double *)part_primal,
-                           (int64_t)n.G + n.L, (const double *)part_dual, (int64_t)n.B, n.rho,
+                           (int64_t)n.B, (const double *)part_dual, (int64_t)n.B, n.rho,
                            d_resid + 2 * (int64_t)(iters - 1));
     HIP_TRY(hipGetLastError());
     return TRON_OK;
