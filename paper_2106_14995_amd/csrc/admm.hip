@@ -233,14 +233,35 @@ __global__ __launch_bounds__(kBlock) void branch_kernel(Net n, double *s, mt::Op
 // belongs to one bus: a generator's powers, a branch end's flows, w and theta, and the flow
 // copy z of the end's p): lam += rho (y - yt), mu += rho (z - p); with gen_next, the
 // generator update of the next iteration from the new copies and multipliers.
-// One thread per bus. The state was just written by kernels running on every XCD, so most
-// loads miss this XCD's L2 and each round of dependent loads costs about a microsecond. A bus
-// with at most kFastG generators and kFastE branch ends therefore loads everything it needs
-// in three rounds (its own data and CSR bounds; the neighbour indices; every neighbour value
-// both passes use) and keeps it in registers; larger buses take the general path. Both paths
-// perform the same operations in the same order. Residual parts per bus: the squared
-// primal residuals of its couplings and the squared changes of its copies.
-constexpr int kFastG = 4, kFastE = 16;
+// Sixteen lanes per bus (one row of the wave's DPP rows): lane j takes the bus's generators
+// and branch ends j, j + 16, ...; the sums over them are per-lane sums combined by a butterfly
+// inside the row, which leaves the same bits in all sixteen lanes. The state was just written
+// by kernels running on every XCD, so most loads miss this XCD's L2 and each round of
+// dependent loads costs about a microsecond: a lane loads its first generator and first end
+// in three rounds (the bus's CSR bounds; the neighbour indices; the neighbour values both
+// passes use) and keeps them in registers; further ones (buses with more than sixteen) are
+// read again in the second pass. Residual parts per bus: the squared primal residuals of its
+// couplings and the squared changes of its copies.
+constexpr int kBusLanes = 16;
+
+template <int CTRL>
+__device__ inline double dpp_row(double v)
+{
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// sum over the 16 lanes of a DPP row, the same bits in each (every step adds two partners'
+// values, commutatively): pairs, quads, half-rows, rows
+__device__ inline double row_sum(double v)
+{
+    v += dpp_row<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_row<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_row<0x141>(v);  // row_half_mirror
+    v += dpp_row<0x140>(v);  // row_mirror
+    return v;
+}
 
 struct BusSums {
     double sgp = 0.0, sgq = 0.0, sep = 0.0, seq = 0.0, sw = 0.0, sth = 0.0;
@@ -306,128 +327,125 @@ __device__ inline void end_duals(const Net &n, const View &v, int64_t l, int e, 
 __global__ __launch_bounds__(kBlock) void bus_kernel(Net n, double *s, double *part_primal, double *part_dual,
                                                      int gen_next)
 {
-    const int64_t b = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (b >= n.B) return;
+    const int64_t b = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kBusLanes;
+    const int j = threadIdx.x & (kBusLanes - 1);
+    // rows past the last bus compute on bus 0 and store nothing, so that every lane of a row
+    // takes part in its sums
+    const bool own = b < n.B;
+    const int64_t bb = own ? b : 0;
     View v = split(s, n.G, n.L, n.B);
     const double rho = n.rho;
-    const int g0 = n.bg_ptr[b], g1 = n.bg_ptr[b + 1];
-    const int e0 = n.be_ptr[b], e1 = n.be_ptr[b + 1];
+    const int g0 = n.bg_ptr[bb], g1 = n.bg_ptr[bb + 1];
+    const int e0 = n.be_ptr[bb], e1 = n.be_ptr[bb + 1];
     double ld[4];
-    MT_UNROLL for (int k = 0; k < 4; k++) ld[k] = n.load[4 * b + k];
-    const double wt0 = v.wt[b], tht0 = v.tht[b];
+    MT_UNROLL for (int k = 0; k < 4; k++) ld[k] = n.load[4 * bb + k];
+    const double wt0 = v.wt[bb], tht0 = v.tht[bb];
     const int ng = g1 - g0, ne = e1 - e0;
-    BusSums t;
-    double d2 = 0.0, p2 = 0.0;
-    if (ng <= kFastG && ne <= kFastE) {
-        int gi[kFastG], code[kFastE];
-        MT_UNROLL for (int u = 0; u < kFastG; u++) gi[u] = u < ng ? n.bg_idx[g0 + u] : -1;
-        MT_UNROLL for (int u = 0; u < kFastE; u++) code[u] = u < ne ? n.be_idx[e0 + u] : -1;
-        double pg[kFastG], lpg[kFastG], qg[kFastG], lqg[kFastG], pgt[kFastG], qgt[kFastG];
-        MT_UNROLL for (int u = 0; u < kFastG; u++) {
-            const int g = gi[u] < 0 ? 0 : gi[u];
-            pg[u] = v.pg[g]; lpg[u] = v.lpg[g]; qg[u] = v.qg[g]; lqg[u] = v.lqg[g];
-            pgt[u] = v.pgt[g]; qgt[u] = v.qgt[g];
-        }
-        double yp[kFastE], yq[kFastE], yw[kFastE], yth[kFastE], lp[kFastE], lq[kFastE], lw[kFastE], lth[kFastE];
-        double otp[kFastE], otq[kFastE], z[kFastE], mu[kFastE];
-        MT_UNROLL for (int u = 0; u < kFastE; u++) {
-            const int c = code[u] < 0 ? 0 : code[u];
-            const int64_t l = c >> 1;
-            const int e = c & 1;
-            const double *y = v.y + 8 * l, *la = v.lam + 8 * l, *yt = v.yt + 4 * l;
-            yp[u] = y[2 * e]; yq[u] = y[2 * e + 1]; yw[u] = y[4 + e]; yth[u] = y[6 + e];
-            lp[u] = la[2 * e]; lq[u] = la[2 * e + 1]; lw[u] = la[4 + e]; lth[u] = la[6 + e];
-            otp[u] = yt[2 * e]; otq[u] = yt[2 * e + 1];
-            z[u] = v.x[6 * l + 4 + e]; mu[u] = v.mu[2 * l + e];
-        }
-        MT_UNROLL for (int u = 0; u < kFastG; u++)
-            if (u < ng) {
-                t.sgp += pg[u] + lpg[u] / rho;
-                t.sgq += qg[u] + lqg[u] / rho;
-            }
-        MT_UNROLL for (int u = 0; u < kFastE; u++)
-            if (u < ne) {
-                t.sep += yp[u] + lp[u] / rho;
-                t.seq += yq[u] + lq[u] / rho;
-                t.sw += yw[u] + lw[u] / rho;
-                t.sth += yth[u] + lth[u] / rho;
-            }
-        const BusSolve r = bus_solve(n, b, t, ng, ne, ld);
-        MT_UNROLL for (int u = 0; u < kFastG; u++)
-            if (u < ng) {
-                const double np = pg[u] + lpg[u] / rho - r.up / rho;
-                const double nq = qg[u] + lqg[u] / rho - r.uq / rho;
-                d2 += (np - pgt[u]) * (np - pgt[u]) + (nq - qgt[u]) * (nq - qgt[u]);
-                v.pgt[gi[u]] = np;
-                v.qgt[gi[u]] = nq;
-                gen_duals(n, v, gi[u], pg[u], qg[u], lpg[u], lqg[u], np, nq, gen_next, p2);
-            }
-        const double dw = r.wnew - wt0, dt = r.tnew - tht0;
-        MT_UNROLL for (int u = 0; u < kFastE; u++)
-            if (u < ne) {
-                const int64_t l = code[u] >> 1;
-                const int e = code[u] & 1;
-                const double np = yp[u] + lp[u] / rho + r.up / rho;
-                const double nq = yq[u] + lq[u] / rho + r.uq / rho;
-                d2 += (np - otp[u]) * (np - otp[u]) + (nq - otq[u]) * (nq - otq[u]);
-                d2 += dw * dw + dt * dt;
-                double *yt = v.yt + 4 * l;
-                yt[2 * e] = np;
-                yt[2 * e + 1] = nq;
-                const double ye[4] = {yp[u], yq[u], yw[u], yth[u]}, le[4] = {lp[u], lq[u], lw[u], lth[u]};
-                end_duals(n, v, l, e, ye, le, z[u], mu[u], np, nq, r.wnew, r.tnew, p2);
-            }
-        v.wt[b] = r.wnew;
-        v.tht[b] = r.tnew;
-    } else {
-        for (int k = g0; k < g1; k++) {
-            const int g = n.bg_idx[k];
-            t.sgp += v.pg[g] + v.lpg[g] / rho;
-            t.sgq += v.qg[g] + v.lqg[g] / rho;
-        }
-        for (int k = e0; k < e1; k++) {
-            const int code = n.be_idx[k];
-            const int64_t l = code >> 1;
-            const int e = code & 1;
-            const double *y = v.y + 8 * l, *la = v.lam + 8 * l;
-            t.sep += y[2 * e] + la[2 * e] / rho;
-            t.seq += y[2 * e + 1] + la[2 * e + 1] / rho;
-            t.sw += y[4 + e] + la[4 + e] / rho;
-            t.sth += y[6 + e] + la[6 + e] / rho;
-        }
-        const BusSolve r = bus_solve(n, b, t, ng, ne, ld);
-        for (int k = g0; k < g1; k++) {
-            const int g = n.bg_idx[k];
-            const double pg = v.pg[g], qg = v.qg[g], lpg = v.lpg[g], lqg = v.lqg[g];
-            const double np = pg + lpg / rho - r.up / rho;
-            const double nq = qg + lqg / rho - r.uq / rho;
-            d2 += (np - v.pgt[g]) * (np - v.pgt[g]) + (nq - v.qgt[g]) * (nq - v.qgt[g]);
-            v.pgt[g] = np;
-            v.qgt[g] = nq;
-            gen_duals(n, v, g, pg, qg, lpg, lqg, np, nq, gen_next, p2);
-        }
-        const double dw = r.wnew - wt0, dt = r.tnew - tht0;
-        for (int k = e0; k < e1; k++) {
-            const int code = n.be_idx[k];
-            const int64_t l = code >> 1;
-            const int e = code & 1;
-            const double *y = v.y + 8 * l, *la = v.lam + 8 * l;
-            double *yt = v.yt + 4 * l;
-            const double ye[4] = {y[2 * e], y[2 * e + 1], y[4 + e], y[6 + e]};
-            const double le[4] = {la[2 * e], la[2 * e + 1], la[4 + e], la[6 + e]};
-            const double np = ye[0] + le[0] / rho + r.up / rho;
-            const double nq = ye[1] + le[1] / rho + r.uq / rho;
-            d2 += (np - yt[2 * e]) * (np - yt[2 * e]) + (nq - yt[2 * e + 1]) * (nq - yt[2 * e + 1]);
-            d2 += dw * dw + dt * dt;
-            yt[2 * e] = np;
-            yt[2 * e + 1] = nq;
-            end_duals(n, v, l, e, ye, le, v.x[6 * l + 4 + e], v.mu[2 * l + e], np, nq, r.wnew, r.tnew, p2);
-        }
-        v.wt[b] = r.wnew;
-        v.tht[b] = r.tnew;
+    // the lane's first generator and first branch end, kept in registers for both passes
+    const bool hg = j < ng, he = j < ne;
+    const int gi = hg ? n.bg_idx[g0 + j] : 0;
+    const int code = he ? n.be_idx[e0 + j] : 0;
+    const int64_t l = code >> 1;
+    const int e = code & 1;
+    double pg = 0.0, qg = 0.0, lpg = 0.0, lqg = 0.0, pgt = 0.0, qgt = 0.0;
+    if (hg) {
+        pg = v.pg[gi]; qg = v.qg[gi]; lpg = v.lpg[gi]; lqg = v.lqg[gi]; pgt = v.pgt[gi]; qgt = v.qgt[gi];
     }
-    part_primal[b] = p2;
-    part_dual[b] = d2;
+    double ye[4] = {0.0, 0.0, 0.0, 0.0}, le[4] = {0.0, 0.0, 0.0, 0.0}, ot[2] = {0.0, 0.0}, z = 0.0, mu = 0.0;
+    if (he) {
+        const double *y = v.y + 8 * l, *la = v.lam + 8 * l, *yt = v.yt + 4 * l;
+        ye[0] = y[2 * e]; ye[1] = y[2 * e + 1]; ye[2] = y[4 + e]; ye[3] = y[6 + e];
+        le[0] = la[2 * e]; le[1] = la[2 * e + 1]; le[2] = la[4 + e]; le[3] = la[6 + e];
+        ot[0] = yt[2 * e]; ot[1] = yt[2 * e + 1];
+        z = v.x[6 * l + 4 + e]; mu = v.mu[2 * l + e];
+    }
+    BusSums t;
+    if (hg) {
+        t.sgp = pg + lpg / rho;
+        t.sgq = qg + lqg / rho;
+    }
+    for (int k = g0 + j + kBusLanes; k < g1; k += kBusLanes) {
+        const int g = n.bg_idx[k];
+        t.sgp += v.pg[g] + v.lpg[g] / rho;
+        t.sgq += v.qg[g] + v.lqg[g] / rho;
+    }
+    if (he) {
+        t.sep = ye[0] + le[0] / rho;
+        t.seq = ye[1] + le[1] / rho;
+        t.sw = ye[2] + le[2] / rho;
+        t.sth = ye[3] + le[3] / rho;
+    }
+    for (int k = e0 + j + kBusLanes; k < e1; k += kBusLanes) {
+        const int c = n.be_idx[k];
+        const int64_t lk = c >> 1;
+        const int ek = c & 1;
+        const double *y = v.y + 8 * lk, *la = v.lam + 8 * lk;
+        t.sep += y[2 * ek] + la[2 * ek] / rho;
+        t.seq += y[2 * ek + 1] + la[2 * ek + 1] / rho;
+        t.sw += y[4 + ek] + la[4 + ek] / rho;
+        t.sth += y[6 + ek] + la[6 + ek] / rho;
+    }
+    t.sgp = row_sum(t.sgp);
+    t.sgq = row_sum(t.sgq);
+    t.sep = row_sum(t.sep);
+    t.seq = row_sum(t.seq);
+    t.sw = row_sum(t.sw);
+    t.sth = row_sum(t.sth);
+    const BusSolve r = bus_solve(n, bb, t, ng, ne, ld);
+    double d2 = 0.0, p2 = 0.0;
+    if (hg && own) {
+        const double np = pg + lpg / rho - r.up / rho;
+        const double nq = qg + lqg / rho - r.uq / rho;
+        d2 += (np - pgt) * (np - pgt) + (nq - qgt) * (nq - qgt);
+        v.pgt[gi] = np;
+        v.qgt[gi] = nq;
+        gen_duals(n, v, gi, pg, qg, lpg, lqg, np, nq, gen_next, p2);
+    }
+    for (int k = g0 + j + kBusLanes; own && k < g1; k += kBusLanes) {
+        const int g = n.bg_idx[k];
+        const double pk = v.pg[g], qk = v.qg[g], lpk = v.lpg[g], lqk = v.lqg[g];
+        const double np = pk + lpk / rho - r.up / rho;
+        const double nq = qk + lqk / rho - r.uq / rho;
+        d2 += (np - v.pgt[g]) * (np - v.pgt[g]) + (nq - v.qgt[g]) * (nq - v.qgt[g]);
+        v.pgt[g] = np;
+        v.qgt[g] = nq;
+        gen_duals(n, v, g, pk, qk, lpk, lqk, np, nq, gen_next, p2);
+    }
+    const double dw = r.wnew - wt0, dt = r.tnew - tht0;
+    if (he && own) {
+        const double np = ye[0] + le[0] / rho + r.up / rho;
+        const double nq = ye[1] + le[1] / rho + r.uq / rho;
+        d2 += (np - ot[0]) * (np - ot[0]) + (nq - ot[1]) * (nq - ot[1]);
+        d2 += dw * dw + dt * dt;
+        double *yt = v.yt + 4 * l;
+        yt[2 * e] = np;
+        yt[2 * e + 1] = nq;
+        end_duals(n, v, l, e, ye, le, z, mu, np, nq, r.wnew, r.tnew, p2);
+    }
+    for (int k = e0 + j + kBusLanes; own && k < e1; k += kBusLanes) {
+        const int c = n.be_idx[k];
+        const int64_t lk = c >> 1;
+        const int ek = c & 1;
+        const double *y = v.y + 8 * lk, *la = v.lam + 8 * lk;
+        double *yt = v.yt + 4 * lk;
+        const double yk[4] = {y[2 * ek], y[2 * ek + 1], y[4 + ek], y[6 + ek]};
+        const double lk4[4] = {la[2 * ek], la[2 * ek + 1], la[4 + ek], la[6 + ek]};
+        const double np = yk[0] + lk4[0] / rho + r.up / rho;
+        const double nq = yk[1] + lk4[1] / rho + r.uq / rho;
+        d2 += (np - yt[2 * ek]) * (np - yt[2 * ek]) + (nq - yt[2 * ek + 1]) * (nq - yt[2 * ek + 1]);
+        d2 += dw * dw + dt * dt;
+        yt[2 * ek] = np;
+        yt[2 * ek + 1] = nq;
+        end_duals(n, v, lk, ek, yk, lk4, v.x[6 * lk + 4 + ek], v.mu[2 * lk + ek], np, nq, r.wnew, r.tnew, p2);
+    }
+    d2 = row_sum(d2);
+    p2 = row_sum(p2);
+    if (own && j == 0) {
+        v.wt[b] = r.wnew;
+        v.tht[b] = r.tnew;
+        part_primal[b] = p2;
+        part_dual[b] = d2;
+    }
 }
 
 // one workgroup of kReduce threads (see reduce_parts64)
@@ -601,7 +619,7 @@ extern "C" tron_err admm_step(admm *a, int32_t iters, double *d_resid, void *str
         hipLaunchKernelGGL(branch_kernel, dim3(grid_for(n.L) + (prev ? 1u : 0u)), dim3(kBlock), lds, st, n,
                            a->d_state, opt, a->d_f, a->d_status, a->d_iters, (const double *)part_primal,
                            (const double *)part_dual, prev);
-        hipLaunchKernelGGL(bus_kernel, dim3(grid_for(n.B)), dim3(kBlock), 0, st, n, a->d_state, part_primal,
+        hipLaunchKernelGGL(bus_kernel, dim3(grid_for((int64_t)n.B * kBusLanes)), dim3(kBlock), 0, st, n, a->d_state, part_primal,
                            part_dual, (int)(it + 1 < iters));
     }
     // the last iteration's residuals
