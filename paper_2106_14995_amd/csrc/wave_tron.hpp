@@ -6,7 +6,8 @@
 // row stride ld >= n + 1 (odd, so that both row and column walks touch distinct banks): the
 // Hessian's upper triangle with its diagonal, the factor's strict lower triangle below it,
 // and the factor's pivots in the spare column n. A Hessian-vector product then reads every
-// H_kj from one address, min(j,k) ld + max(j,k), with no special case on the diagonal.
+// H_kj from one address, min(j,k) ld + max(j,k) = min(j,k) (ld - 1) + j + k, with no
+// special case on the diagonal.
 // Every decision of the method is taken on wave-reduced, wave-uniform values (the free set
 // is a 64-bit ballot), so the 64 lanes never diverge.
 // Sums use a butterfly of lane swaps (every lane ends with the same bits); the pivots and
@@ -251,19 +252,15 @@ struct WaveTron {
         return uni(wave_sum(s));
     }
 
-    // LDS index of H_kj (upper triangle, diagonal included): min(j,k) ld + max(j,k), with a
-    // 24-bit multiply-add (indices stay far below 2^24)
-    MT_INLINE int hidx(int k, int j) const
+    // H_kj (upper triangle, diagonal included) sits at min(j,k) ld + max(j,k) = min(j,k)
+    // (ld - 1) + j + k: with blk = M + k + j0 for a block of columns j = j0 + u (u a
+    // constant after unrolling), the j0 + k part is the block's base, u an immediate offset,
+    // and the rest one 24-bit multiply-add into a byte offset (indices stay far below 2^24);
+    // ldb = 8 (ld - 1)
+    MT_INLINE double hrd(const double *blk, unsigned ldb, int k, int j, int u) const
     {
-        const int a = j < k ? j : k, b = j < k ? k : j;
-        return (int)__umul24((unsigned)a, (unsigned)ld) + b;
-    }
-
-    // H_kj for row k (< n), with diag in place of the stored diagonal
-    MT_INLINE double hget(int k, int j, double dg) const
-    {
-        const double h = M[hidx(k, j)];
-        return j == k ? dg : h;
+        const unsigned m = (unsigned)(j < k ? j : k);
+        return *(const double *)((const char *)blk + __umul24(m, ldb) + 8 * u);
     }
 
     // y = H v over the first n rows (H's diagonal read from LDS, as hess() stored it); rows
@@ -276,20 +273,23 @@ struct WaveTron {
             acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
             kk[r] = row(r) < n ? row(r) : 0;
         }
+        const unsigned ldb = 8u * (unsigned)(ld - 1);
         MT_UNROLL for (int rr = 0; rr < R; rr++) {
             const int jend = n - 64 * rr < 64 ? n - 64 * rr : 64;
             int jj = 0;
             for (; jj + 4 <= jend; jj += 4) {
                 double vj[4];
                 MT_UNROLL for (int u = 0; u < 4; u++) vj[u] = bcast(v[rr], jj + u);
-                MT_UNROLL for (int r = 0; r < R; r++)
+                MT_UNROLL for (int r = 0; r < R; r++) {
+                    const double *blk = M + kk[r] + 64 * rr + jj;
                     MT_UNROLL for (int u = 0; u < 4; u++)
-                        acc[r][u] = fma(M[hidx(kk[r], 64 * rr + jj + u)], vj[u], acc[r][u]);
+                        acc[r][u] = fma(hrd(blk, ldb, kk[r], 64 * rr + jj + u, u), vj[u], acc[r][u]);
+                }
             }
             for (; jj < jend; jj++) {
                 const double vj = bcast(v[rr], jj);
                 MT_UNROLL for (int r = 0; r < R; r++)
-                    acc[r][0] = fma(M[hidx(kk[r], 64 * rr + jj)], vj, acc[r][0]);
+                    acc[r][0] = fma(hrd(M + kk[r] + 64 * rr + jj, ldb, kk[r], 64 * rr + jj, 0), vj, acc[r][0]);
             }
         }
         MT_UNROLL for (int r = 0; r < R; r++)
@@ -306,20 +306,29 @@ struct WaveTron {
             acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
             kk[r] = row(r) < n ? row(r) : 0;
         }
+        const unsigned ldb = 8u * (unsigned)(ld - 1);
         MT_UNROLL for (int rr = 0; rr < R; rr++) {
             const int jend = n - 64 * rr < 64 ? n - 64 * rr : 64;
             int jj = 0;
             for (; jj + 4 <= jend; jj += 4) {
                 double vj[4];
                 MT_UNROLL for (int u = 0; u < 4; u++) vj[u] = bcast(v[rr], jj + u);
-                MT_UNROLL for (int r = 0; r < R; r++)
-                    MT_UNROLL for (int u = 0; u < 4; u++)
-                        acc[r][u] = fma(hget(kk[r], 64 * rr + jj + u, diag[r]), vj[u], acc[r][u]);
+                MT_UNROLL for (int r = 0; r < R; r++) {
+                    const double *blk = M + kk[r] + 64 * rr + jj;
+                    MT_UNROLL for (int u = 0; u < 4; u++) {
+                        const int j = 64 * rr + jj + u;
+                        const double h = hrd(blk, ldb, kk[r], j, u);
+                        acc[r][u] = fma(j == kk[r] ? diag[r] : h, vj[u], acc[r][u]);
+                    }
+                }
             }
             for (; jj < jend; jj++) {
                 const double vj = bcast(v[rr], jj);
-                MT_UNROLL for (int r = 0; r < R; r++)
-                    acc[r][0] = fma(hget(kk[r], 64 * rr + jj, diag[r]), vj, acc[r][0]);
+                MT_UNROLL for (int r = 0; r < R; r++) {
+                    const int j = 64 * rr + jj;
+                    const double h = hrd(M + kk[r] + j, ldb, kk[r], j, 0);
+                    acc[r][0] = fma(j == kk[r] ? diag[r] : h, vj, acc[r][0]);
+                }
             }
         }
         MT_UNROLL for (int r = 0; r < R; r++)
