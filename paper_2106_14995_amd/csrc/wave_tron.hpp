@@ -705,13 +705,20 @@ struct WaveTron {
                 }
             }
         } else {
+            // the lane's row of L from column 0 (a row past n reads row 0, its update masked:
+            // its index is taken as -1)
+            const double *lr[R];
+            int ii[R];
+            MT_UNROLL for (int r = 0; r < R; r++) {
+                const int i = row(r);
+                ii[r] = i < n ? i : -1;
+                lr[r] = M + (int)__umul24((unsigned)(i < n ? i : 0), (unsigned)ld);
+            }
             for (int j = 0; j < n; j++) {
                 const double yj = owner_scaled(b, j);
                 MT_UNROLL for (int r = 0; r < R; r++) {
-                    const int i = row(r);
-                    const bool below = i > j && i < n;
-                    const double l = M[below ? (int)__umul24((unsigned)i, (unsigned)ld) + j : 0];
-                    b[r] = fma(-(below ? l : 0.0), yj, b[r]);
+                    const double l = lr[r][j];
+                    b[r] = fma(-(j < ii[r] ? l : 0.0), yj, b[r]);
                 }
             }
         }
@@ -738,13 +745,16 @@ struct WaveTron {
                 }
             }
         } else {
+            // the lane's column of L (entry j at j ld + i; a row past n reads column 0, and
+            // is never above a step)
+            const double *lc[R];
+            MT_UNROLL for (int r = 0; r < R; r++) lc[r] = M + (row(r) < n ? row(r) : 0);
+            const unsigned ldb = 8u * (unsigned)ld;
             for (int j = n - 1; j >= 0; j--) {
                 const double yj = owner_scaled(b, j);
                 MT_UNROLL for (int r = 0; r < R; r++) {
-                    const int i = row(r);
-                    const bool above = i < j;
-                    const double l = M[above ? (int)__umul24((unsigned)j, (unsigned)ld) + i : 0];
-                    b[r] = fma(-(above ? l : 0.0), yj, b[r]);
+                    const double l = *(const double *)((const char *)lc[r] + (unsigned)j * ldb);
+                    b[r] = fma(-(row(r) < j ? l : 0.0), yj, b[r]);
                 }
             }
         }
