@@ -62,7 +62,7 @@ def one_iteration_parity(T, net, warm_iters):
     tol = dict(pg=1e-9, qg=1e-9, pgt=1e-8, qgt=1e-8, lpg=1e-6, lqg=1e-6, x=1e-9, y=1e-8,
                yt=1e-8, lam=1e-6, mu=1e-6, wt=1e-8, tht=1e-8)
     for k, t in tol.items():
-        d = np.abs(gv[k] - ov[k]).max()
+        d = np.abs(gv[k] - ov[k]).max(initial=0.0)  # fields may be empty (no generators)
         assert d <= t, (k, d)
     r = to_np(res)[0]
     assert np.allclose(r, ores[0], rtol=1e-6, atol=1e-9)
@@ -88,6 +88,32 @@ def test_one_iteration_parity_hub_bus(T):
     deg = np.bincount(np.concatenate([hub.br_from, hub.br_to]), minlength=hub.nbus)
     assert deg[0] > 16 and np.sum(hub.gen_bus == 0) > 4
     one_iteration_parity(T, hub, 3)
+
+
+def test_one_iteration_parity_many_generators(T):
+    """A hub bus with more than 16 generators and more than 16 branch ends: the bus kernel
+    gives each of a bus's 16 lanes one generator and one end, and takes the rest in a loop."""
+    hub = W.network(nbus=300, nbranch=420, ngen=60, config_id=97, hub_ends=15, hub_gens=20)
+    deg = np.bincount(np.concatenate([hub.br_from, hub.br_to]), minlength=hub.nbus)
+    assert deg[0] > 16 and np.sum(hub.gen_bus == 0) > 16
+    one_iteration_parity(T, hub, 3)
+
+
+def test_network_without_generators(T):
+    """No generators and no loads: every flow of the initial state is zero, so the iteration
+    leaves it in place (the branch solves stop at their first convergence test and only set
+    their Cauchy step to 1); the generator kernel is never launched and no bus has generator
+    lanes. After five iterations both sides hold the same state, bit for bit, with zero
+    residuals."""
+    empty = W.network(nbus=100, nbranch=150, ngen=0, config_id=96)
+    one_iteration_parity(T, empty, 3)
+    a = T.Admm(empty)
+    r = to_np(a.step(5))
+    g5 = to_np(a.get_state())
+    a.close()
+    o5, ro = oracle.admm_run(empty, oracle.admm_init(empty), 5)
+    assert np.array_equal(g5, o5)
+    assert np.all(r == 0.0) and np.all(np.asarray(ro) == 0.0)
 
 
 def test_branch_solutions_are_kkt_points(T, net):
