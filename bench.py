@@ -409,17 +409,19 @@ def bench_design(args):
 def bench_groups(args):
     """The group-width sweep (section 4.2's thread configuration): one instance per G lanes,
     G = 1 (the lane kernel), 2, 4, 8, 16, or the whole 64-lane wavefront (the wave kernel),
-    on uniform batches of the quartic family, the hs45 variant and the branch batch. Each
-    figure is the time of one solve of the batch (mean of the timed steps)."""
+    on uniform batches of 16,384 instances of the quartic family and of the hs45 variant
+    (random starts) for every n = 1..32, with every width that has a build at that n (1, 2, 4,
+    8 and 64 lanes up to n = 8; 8, 16 and 64 up to 16; the wavefront above), and on the
+    65,536-instance branch batch. Each figure is the time of one solve of the batch (mean of
+    the timed steps); the summary names the fastest width per family and n."""
     import torch
     from paper_2106_14995_amd import tron
     from paper_2106_14995_amd import workloads as W
     stream = torch.cuda.current_stream()
     rows = []
 
-    def run(label, fam, bt, n, spec):
+    def run(label, fam, bt, n, spec, dev):
         h = tron.Batch(fam, n, batch=bt.batch, spec=spec)
-        dev = tron.to_device(bt)
         lat, total = time_solves(lambda: h.solve(*dev, stream=stream), args.steps, args.warmup, stream)
         _, _, st, it = h.solve(*dev, stream=stream)
         torch.cuda.synchronize()
@@ -431,26 +433,32 @@ def bench_groups(args):
         log(f"{label} n={n} G={row['lanes_per_instance']}: {row['ms_per_batch']:.4f} ms")
 
     br = W.br6_batch(65536, config_id=1)
+    dev = tron.to_device(br)
     for g in (1, 2, 4, 8):
-        run("br6", W.BR6, br, 6, tron.plan_spec(lane_group=g))
-    for n in (4, 8):
-        bt = W.qp4_batch(16384, n, config_id=120 + n)
-        for g in (1, 2, 4, 8):
-            run("qp4", W.QP4, bt, n, tron.plan_spec(lane_group=g))
-        run("qp4", W.QP4, bt, n, tron.plan_spec(lane_max_n=0))
-    for n in (12, 16):
-        bt = W.qp4_batch(16384, n, config_id=120 + n)
-        for g in (8, 16):
-            run("qp4", W.QP4, bt, n, tron.plan_spec(group16=g))
-        run("qp4", W.QP4, bt, n, tron.plan_spec())
-    for n in (8, 16):
-        bt = W.hs45m_random_start(16384, n, config_id=130 + n)
-        specs = [tron.plan_spec(lane_group=g) for g in (1, 2, 4, 8)] if n <= 8 else \
-            [tron.plan_spec(group16=g) for g in (8, 16)] + [tron.plan_spec()]
-        for sp in specs:
-            run("hs45m_random_start", W.HS45M, bt, n, sp)
+        run("br6", W.BR6, br, 6, tron.plan_spec(lane_group=g), dev)
+    for label, fam in (("qp4", W.QP4), ("hs45m_random_start", W.HS45M)):
+        for n in range(1, 33):
+            bt = W.qp4_batch(16384, n, config_id=120 + n) if fam == W.QP4 else \
+                W.hs45m_random_start(16384, n, config_id=130 + n)
+            dev = tron.to_device(bt)
+            if n <= 8:
+                specs = [tron.plan_spec(lane_group=g) for g in (1, 2, 4, 8)] + [tron.plan_spec(lane_max_n=0)]
+            elif n <= 16:
+                specs = [tron.plan_spec(group16=g) for g in (8, 16)] + [tron.plan_spec()]
+            else:
+                specs = [tron.plan_spec()]
+            for sp in specs:
+                run(label, fam, bt, n, sp, dev)
+            del dev
+    best = {}
+    for r in rows:
+        k = (r["case"], r["n"])
+        if k not in best or r["ms_per_batch"] < best[k]["ms_per_batch"]:
+            best[k] = r
+    summary = [{"case": c, "n": n, "best_lanes_per_instance": r["lanes_per_instance"],
+                "ms_per_batch": r["ms_per_batch"]} for (c, n), r in sorted(best.items())]
     print(json.dumps({"config": "group-width sweep: uniform batches, one solve per step, gtol 1e-6",
-                      "rows": rows}), flush=True)
+                      "rows": rows, "best": summary}), flush=True)
 
 
 def bench_workspace(args):
