@@ -259,8 +259,15 @@ struct WaveTron {
     // ldb = 8 (ld - 1)
     MT_INLINE double hrd(const double *blk, unsigned ldb, int k, int j, int u) const
     {
-        const unsigned m = (unsigned)(j < k ? j : k);
-        return *(const double *)((const char *)blk + __umul24(m, ldb) + 8 * u);
+        if constexpr (kGlobal) {
+            // in global memory a 32-bit element index off the wave's uniform base keeps the
+            // loads in their scalar-base form (a per-lane 64-bit base costs more than it saves)
+            const int a = j < k ? j : k, b = j < k ? k : j;
+            return M[(int)__umul24((unsigned)a, (unsigned)ld) + b];
+        } else {
+            const unsigned m = (unsigned)(j < k ? j : k);
+            return *(const double *)((const char *)blk + __umul24(m, ldb) + 8 * u);
+        }
     }
 
     // y = H v over the first n rows (H's diagonal read from LDS, as hess() stored it); rows
