@@ -121,7 +121,9 @@ tron_err tron_batch_create(tron_batch **out, tron_family family, int64_t batch,
  * kernel rather than one per size) for batches of mixed sizes up to n = 128: one launch
  * solves every wavefront instance, with one workgroup of pool_waves (8 or 12) wavefronts
  * per CU sharing the CU's LDS as a pool; each wave claims instances from the batch's list
- * ordered largest n first and reserves exactly the LDS its instance needs; a second launch
+ * (largest n first, each of the largest followed by as many of the smallest as fill the
+ * CU's other waves while its pool holds the largest) and reserves exactly the LDS its
+ * instance needs; a second launch
  * solves every lane instance, in packs of 64 of one size. Edges and streams are then unused. */
 typedef struct {
     int32_t lane_max_n;   /* 0..8 */

@@ -306,9 +306,10 @@ static bool has_wave_kernel(tron_family fam) { return fam == TRON_FAMILY_QP4 || 
 // persistent size-bucketed launch: one launch for every wavefront instance of a mixed batch
 // ------------------------------------------------------------------------------------
 // A workgroup of kWaves wavefronts owns one CU's LDS as a pool of kPoolPage-byte pages. Each
-// wave loops on its own: claim the next instance of the batch's list (ordered largest n
-// first, so the costliest start first and the cheapest fill in at the end), reserve the
-// instance's matrix array (n ((n+1)|1) doubles) in the pool, solve it, release the pages.
+// wave loops on its own: claim the next instance of the batch's list (the largest
+// instances first, each followed by small ones to fill the waves beside it; see
+// build_pool_plan), reserve the instance's matrix array (n ((n+1)|1) doubles) in the pool,
+// solve it, release the pages.
 // Instances of every size thus run side by side on every CU, packed by their actual LDS
 // need, with no bucket waiting for a stream or a hardware queue.
 constexpr int kPoolPage = 512;
@@ -677,9 +678,9 @@ static lane_launch_fn mid_launcher(tron_family fam, const tron_plan_spec &sp, in
     return mt_group_launcher(fam, 16, sp.group16);
 }
 
-// The persistent form: the wavefront instances ordered largest n first (the costliest start
-// first; within one n, instance order), and the lane instances grouped by size into packs of
-// 64 (the last pack of a size padded with -1).
+// The persistent form: the wavefront instances sorted largest n first (within one n,
+// instance order) and then interleaved from both ends (below), and the lane instances
+// grouped by size into packs of 64 (the last pack of a size padded with -1).
 static tron_err build_pool_plan(tron_batch *h, const std::vector<int32_t> &n, hipStream_t st)
 {
     const tron_plan_spec &sp = h->spec;
@@ -719,6 +720,26 @@ static tron_err build_pool_plan(tron_batch *h, const std::vector<int32_t> &n, hi
     if (h->pool_nmax > 0 &&
         (int64_t)h->pool_pages * kPoolPage < mt_wave_matrix_doubles(h->pool_nmax) * (int64_t)sizeof(double))
         return mt_fail(TRON_ERR_UNSUPPORTED, "n = %d does not fit the LDS pool", h->pool_nmax);
+    // Claim order. Largest first keeps the costliest instances from ending the launch, but a
+    // CU's pool holds only `fit` of the largest at once, and its other waves would sleep until
+    // pages free up. So each of the largest is followed by enough of the smallest to fill the
+    // CU's waves beside them (the two ends of the sorted list meet in the middle); when every
+    // instance fits beside the others the order stays largest first.
+    if (!wave.empty()) {
+        const int64_t big = (mt_wave_matrix_doubles(h->pool_nmax) * (int64_t)sizeof(double) + kPoolPage - 1) / kPoolPage;
+        const int fit = std::max(1, (int)(h->pool_pages / big));
+        const int small_per_big = std::max(0, sp.pool_waves / fit - 1);
+        if (small_per_big > 0) {
+            std::vector<int32_t> o;
+            o.reserve(wave.size());
+            size_t f = 0, b = wave.size();
+            while (f < b) {
+                o.push_back(wave[f++]);
+                for (int k = 0; k < small_per_big && f < b; k++) o.push_back(wave[--b]);
+            }
+            wave.swap(o);
+        }
+    }
     HIP_TRY(hipMalloc(&h->d_counter, sizeof(int32_t)));
     if (!wave.empty()) {
         HIP_TRY(hipMalloc(&h->d_pool_index, sizeof(int32_t) * wave.size()));
