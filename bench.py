@@ -177,7 +177,8 @@ def bench_uneven(args):
                status=torch.empty(B, dtype=torch.int32, device="cuda"),
                iters=torch.empty(B, dtype=torch.int32, device="cuda"))
     res = {"config": f"qp4 uneven, {B} instances, n log-uniform in [4,64], gtol 1e-6"}
-    plans = [("bucketed_streams", None, False), ("bucketed_graph", None, True),
+    plans = [("bucketed_streams", tron.plan_spec(pool_waves=0), False),
+             ("bucketed_graph", tron.plan_spec(pool_waves=0), True),
              ("persistent_8_graph", tron.plan_spec(pool_waves=8), True),
              ("persistent_12_graph", tron.plan_spec(pool_waves=12), True)]
     if args.plan:
@@ -234,7 +235,9 @@ def bench_uneven(args):
                            "note": "wave instances with n > 16 use FP64 matrix-core products in their "
                                    "factorisation; the peak is the FP64 vector one"}
         # HBM bytes of the persistent launch's wavefront kernel, from its committed counters
-        if best_key == "persistent_12_graph":
+        # (that plan, or an autotuned plan that chose the same launch)
+        tuned_pool12 = best_key == "autotuned_graph" and res[best_key].get("plan", {}).get("pool_waves") == 12
+        if best_key == "persistent_12_graph" or tuned_pool12:
             kname = "pool_kernel<mt::WaveFamQP4<1>, mt::WaveFamQP4<1>, 12>"
             tr = measured_traffic(kname)
             if tr is not None:

@@ -131,7 +131,7 @@ typedef struct {
     int32_t edges[16];
     int32_t streams;      /* 1..8 */
     int32_t lane_block;   /* 64 or 256 */
-    int32_t pool_waves;   /* 0 (bucketed), 8 or 12 (persistent)                                */
+    int32_t pool_waves;   /* 0 (bucketed), 8 or 12 (persistent; mixed-size batches only)      */
     int32_t lane_group;   /* lanes per instance for n <= lane_max_n: 1 (lane kernel), 2, 4 or 8
                              (the group kernel: one instance per group of lanes, rows split
                              over the group, section 4.2's thread configuration), or 0:
@@ -145,7 +145,9 @@ typedef struct {
 } tron_plan_spec;
 
 /* lane_max_n 8, edges 16/24/32/40/48/56/64/80/96/112/128, 4 streams, lane_block 64,
- * pool_waves 0, lane_group 0 (automatic), group16 0, wave_global 0. */
+ * pool_waves 12 (a batch of mixed sizes up to n = 128 runs the persistent launch; uniform
+ * batches and mixed batches beyond 128 use the buckets), lane_group 0 (automatic),
+ * group16 0, wave_global 0. */
 void tron_default_plan_spec(tron_plan_spec *spec);
 /* tron_batch_create with an explicit plan (spec NULL = default). INVALID for a bad spec,
  * UNSUPPORTED when some n exceeds the largest edge. */

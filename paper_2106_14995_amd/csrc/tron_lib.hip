@@ -548,7 +548,7 @@ static void default_spec(tron_plan_spec *p)
     for (int i = 0; i < 16; i++) p->edges[i] = i < kN ? e[i] : 0;
     p->streams = kMaxSideStreams;
     p->lane_block = 64;
-    p->pool_waves = 0;
+    p->pool_waves = 12;  // mixed batches: the persistent launch (uniform batches use buckets)
     p->lane_group = 0;
     p->group16 = 0;
     p->wave_global = 0;
@@ -1312,6 +1312,7 @@ extern "C" tron_err tron_autotune(tron_family fam, int64_t batch, const int32_t 
     };
     tron_plan_spec cur;
     default_spec(&cur);
+    cur.pool_waves = 0;  // stages 1-3 tune the bucketed form, stage 4 the persistent one
     double cur_ms = 1e30;
     tron_err rc = TRON_OK;
     // stage 1: bucket edges x streams
@@ -1319,6 +1320,7 @@ extern "C" tron_err tron_autotune(tron_family fam, int64_t batch, const int32_t 
         for (int streams : {1, 4}) {
             tron_plan_spec sp;
             default_spec(&sp);
+            sp.pool_waves = 0;
             sp.nedges = (int)es.size();
             for (int i = 0; i < sp.nedges; i++) sp.edges[i] = es[i];
             sp.streams = streams;

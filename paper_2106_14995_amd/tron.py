@@ -520,10 +520,10 @@ class Server:
 DEFAULT_EDGES = (16, 24, 32, 40, 48, 56, 64, 80, 96, 112, 128)
 
 
-def plan_spec(lane_max_n=8, edges=DEFAULT_EDGES, streams=4, lane_block=64, pool_waves=0,
+def plan_spec(lane_max_n=8, edges=DEFAULT_EDGES, streams=4, lane_block=64, pool_waves=12,
               lane_group=0, group16=0, wave_global=0) -> PlanSpec:
     """A launch plan (the defaults are the library's default plan); pool_waves 8 or 12 selects
-    the persistent launch; lane_group 1/2/4/8 puts each instance with n <= lane_max_n on that
+    the persistent launch for batches of mixed sizes up to n = 128 (0: the buckets); lane_group 1/2/4/8 puts each instance with n <= lane_max_n on that
     many lanes (0: automatic, 8 for uniform quartic batches of n = 7 or 8 up to 16,384
     instances, else 1); group16 8/16 puts lane_max_n < n <= 16 on groups of that width; wave_global 1
     keeps the quartic family's wavefront matrices in global memory instead of LDS."""

@@ -55,7 +55,7 @@ def test_default_plan_spec_matches_the_binding():
     mine = tron.plan_spec()
     assert spec.lane_max_n == mine.lane_max_n and spec.streams == mine.streams
     assert spec.lane_block == mine.lane_block == 64
-    assert spec.pool_waves == mine.pool_waves == 0
+    assert spec.pool_waves == mine.pool_waves == 12
     assert spec.lane_group == mine.lane_group == 0 and spec.group16 == mine.group16 == 0
     assert spec.wave_global == mine.wave_global == 0
     assert list(spec.edges[:spec.nedges]) == list(tron.DEFAULT_EDGES) == list(mine.edges[:mine.nedges])

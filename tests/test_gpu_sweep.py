@@ -36,10 +36,12 @@ def tron():
 
 
 def _spec(T, name):
+    # the default plan runs a mixed batch on the persistent launch; the other options shape
+    # the bucketed plan
     return {"default": None, "pool12": T.plan_spec(pool_waves=12), "pool8": T.plan_spec(pool_waves=8),
-            "group8": T.plan_spec(lane_group=8), "group4": T.plan_spec(lane_group=4),
-            "g16": T.plan_spec(group16=16), "lane256": T.plan_spec(lane_block=256),
-            "global": T.plan_spec(wave_global=1)}[name]
+            "group8": T.plan_spec(lane_group=8, pool_waves=0), "group4": T.plan_spec(lane_group=4, pool_waves=0),
+            "g16": T.plan_spec(group16=16, pool_waves=0), "lane256": T.plan_spec(lane_block=256, pool_waves=0),
+            "global": T.plan_spec(wave_global=1, pool_waves=0)}[name]
 
 
 @pytest.mark.parametrize("cid,kind,plan,salt", _draws(20261203, 24))

@@ -113,7 +113,8 @@ def test_uneven_full_size(tron):
     sizes, bt, dev, out = _uneven_setup(tron)
     ref = oracle_ref(bt)
     spec, _ = tron.autotune(W.QP4, sizes, *dev, out["x"], out["f"], out["status"], out["iters"], reps=1)
-    for name, sp in (("default plan", None), ("autotuned plan", spec)):
+    for name, sp in (("default plan", None), ("bucketed plan", tron.plan_spec(pool_waves=0)),
+                     ("autotuned plan", spec)):
         g = _run_plan(tron, sizes, dev, out, spec=sp)
         assert np.all(g["status"] == 0)
         check_parity(bt, g, ref, convex=True, label="uneven 50000, " + name)
@@ -338,10 +339,11 @@ def test_graph_replays_match_eager(tron):
     sizes = W.loguniform_sizes(900, 2, 72, config_id=34)
     bt = W.qp4_batch(900, sizes, config_id=34)
     dev = tron.to_device(bt)
-    eager = tron.Batch(W.QP4, sizes)
+    buckets = tron.plan_spec(pool_waves=0)
+    eager = tron.Batch(W.QP4, sizes, spec=buckets)
     xe, fe, se, ie = [t.clone() for t in eager.solve(*dev)]
     torch.cuda.synchronize()
-    g = tron.Batch(W.QP4, sizes, opts=tron.options(graph=True))
+    g = tron.Batch(W.QP4, sizes, opts=tron.options(graph=True), spec=buckets)
     x = torch.empty_like(xe); f = torch.empty_like(fe)
     st = torch.empty_like(se); it = torch.empty_like(ie)
     for rep in range(4):
@@ -372,9 +374,9 @@ def test_plan_specs_and_autotune(tron, tmp_path):
     bt = W.qp4_batch(700, sizes, config_id=35)
     dev = tron.to_device(bt)
     ref = oracle_ref(bt)
-    for spec in (tron.plan_spec(), tron.plan_spec(lane_max_n=4, edges=(12, 24, 48, 96), streams=1,
-                                                  lane_block=64),
-                 tron.plan_spec(lane_max_n=0, edges=(8, 16, 32, 64, 128), streams=2)):
+    for spec in (tron.plan_spec(), tron.plan_spec(pool_waves=0),
+                 tron.plan_spec(lane_max_n=4, edges=(12, 24, 48, 96), streams=1, lane_block=64, pool_waves=0),
+                 tron.plan_spec(lane_max_n=0, edges=(8, 16, 32, 64, 128), streams=2, pool_waves=0)):
         h = tron.Batch(W.QP4, sizes, spec=spec)
         x, f, st, it = h.solve(*dev)
         torch.cuda.synchronize()
@@ -382,7 +384,7 @@ def test_plan_specs_and_autotune(tron, tmp_path):
         h.close()
         check_parity(bt, g, ref, convex=True)
     with pytest.raises(tron.TronError):
-        tron.Batch(W.QP4, sizes, spec=tron.plan_spec(edges=(16, 32, 64)))  # 90 above the last edge
+        tron.Batch(W.QP4, sizes, spec=tron.plan_spec(edges=(16, 32, 64), pool_waves=0))  # 90 above the last edge
     x = torch.empty(int(bt.n.sum()), dtype=torch.float64, device="cuda")
     f = torch.empty(700, dtype=torch.float64, device="cuda")
     st = torch.empty(700, dtype=torch.int32, device="cuda")
@@ -526,7 +528,7 @@ def test_group_kernel_to_16(tron, g):
     no allowance."""
     sizes = W.loguniform_sizes(900, 1, 40, config_id=73)
     bt = W.qp4_batch(900, sizes, config_id=73)
-    spec = tron.plan_spec(group16=g)
+    spec = tron.plan_spec(group16=g, pool_waves=0)  # a bucketed-plan option
     out, plan = _solve_spec(tron, bt, spec)
     mid = [p for p in plan if p["lanes"] == g]
     assert len(mid) == 1 and mid[0]["count"] == int(((sizes > 8) & (sizes <= 16)).sum())
@@ -569,7 +571,7 @@ def test_wave_global_workspace_below_the_lds_limit(tron):
     and two rows per lane, against the oracle; a uniform batch takes the same form."""
     sizes = W.loguniform_sizes(400, 2, 128, config_id=78)
     bt = W.qp4_batch(400, sizes, config_id=78)
-    g, plan = _solve_spec(tron, bt, tron.plan_spec(wave_global=1))
+    g, plan = _solve_spec(tron, bt, tron.plan_spec(wave_global=1, pool_waves=0))  # a bucketed-plan option
     check_parity(bt, g, oracle_ref(bt), convex=True, label="wave_global mixed")
     uni = W.qp4_batch(200, 40, config_id=79)
     g, plan = _solve_spec(tron, uni, tron.plan_spec(wave_global=1))
