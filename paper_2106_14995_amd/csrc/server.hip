@@ -88,11 +88,7 @@ private:
     size_t used_ = 0;
 };
 
-// Wavefront buckets of a launch group (n_max 16, 32, 64, 96, 128): few enough that a group's
-// kernels, which run one after another on its stream, stay long; the split at 96 lets two
-// instances of n <= 96 (74 KB of LDS each) share a CU where one of n_max 128 (132 KB) fills it.
-constexpr int kServeEdges[5] = {16, 32, 64, 96, 128};
-int wave_nmax_of(int n) { return n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : n <= 96 ? 96 : 128; }
+int wave_nmax_of(int n) { return n <= 16 ? 16 : n <= 32 ? 32 : n <= 64 ? 64 : 128; }
 
 struct Session {
     std::vector<int32_t> n;
@@ -236,23 +232,23 @@ void stage_group(tron_server *s, Group *g)
     }
     for (int64_t b = 0; b < 2 * g->B; b++) state[b] = 0.0;  // cold unless a session overwrites it
     // buckets: wave kernels (largest first) then lane kernels of each exact n
-    std::vector<std::vector<int32_t>> wave(5), lane(9);
+    std::vector<std::vector<int32_t>> wave(4), lane(9);
     for (int64_t b = 0; b < g->B; b++) {
         const int ni = all_n[b];
         if (ni <= 8) lane[ni].push_back((int32_t)b);
         else {
             const int w = wave_nmax_of(ni);
-            wave[w == 16 ? 0 : w == 32 ? 1 : w == 64 ? 2 : w == 96 ? 3 : 4].push_back((int32_t)b);
+            wave[w == 16 ? 0 : w == 32 ? 1 : w == 64 ? 2 : 3].push_back((int32_t)b);
         }
     }
     int64_t off = 0;
     g->buckets.clear();
-    for (int w = 4; w >= 0; w--) {
+    for (int w = 3; w >= 0; w--) {
         auto &v = wave[w];
         if (v.empty()) continue;
         std::stable_sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return all_n[a] > all_n[b]; });
         std::memcpy(index + off, v.data(), sizeof(int32_t) * v.size());
-        g->buckets.push_back({kServeEdges[w], 64, off, (int64_t)v.size()});
+        g->buckets.push_back({16 << w, 64, off, (int64_t)v.size()});
         off += (int64_t)v.size();
     }
     for (int k = 8; k >= 1; k--) {
