@@ -412,6 +412,33 @@ def _solve_spec(T, bt, spec, **kw):
     return out, plan
 
 
+def test_default_plan_forms(tron):
+    """The default plan runs a batch of mixed sizes up to n = 128 as one persistent launch
+    (one wavefront entry holding every n > 8 instance, then the lane sizes); pool_waves 0
+    asks for the buckets; a uniform batch, and a mixed batch with an n above 128, take the
+    buckets whatever the spec says."""
+    sizes = W.loguniform_sizes(300, 2, 100, config_id=36)
+    h = tron.Batch(W.QP4, sizes)
+    plan = h.plan()
+    h.close()
+    waves = [b for b in plan if b["lanes"] == 64]
+    assert len(waves) == 1 and waves[0]["count"] == int((sizes > 8).sum()) and waves[0]["nmax"] == int(sizes.max())
+    assert sum(b["count"] for b in plan) == 300
+    h = tron.Batch(W.QP4, sizes, spec=tron.plan_spec(pool_waves=0))
+    plan0 = h.plan()
+    h.close()
+    assert len([b for b in plan0 if b["lanes"] == 64]) > 1
+    assert {b["nmax"] for b in plan0 if b["lanes"] == 64} <= set(tron.DEFAULT_EDGES)
+    assert sum(b["count"] for b in plan0) == 300
+    h = tron.Batch(W.QP4, 40, batch=100)
+    assert h.plan() == [dict(nmax=40, lanes=64, count=100)]
+    h.close()
+    big = np.array([10, 20, 200, 30], dtype=np.int32)
+    h = tron.Batch(W.QP4, big)
+    assert len([b for b in h.plan() if b["lanes"] == 64]) >= 2
+    h.close()
+
+
 @pytest.mark.parametrize("waves", [8, 12])
 def test_pool_plan_uneven_full_size(tron, waves):
     """The uneven benchmark's batch (50,000 quartic problems, n log-uniform in [4,64]) through
